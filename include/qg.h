@@ -1,0 +1,131 @@
+/*
+ * qg.h -- C ABI of libqg, the MI355X (gfx950) query path of SymphonyQG
+ * (Gou, Gao, Xu, Long: "SymphonyQG: Towards Symphonious Integration of
+ * Quantization and Graph for Approximate Nearest Neighbor Search",
+ * arXiv 2411.12229).
+ *
+ * The library owns a quantization-graph index resident in device memory:
+ * one contiguous block per vertex holding its raw vector, the 1-bit RaBitQ
+ * codes and two correction factors of each out-neighbour (normalised with
+ * the vertex itself as the centre), and the neighbour ids (Sec. 3.1.3).
+ * qg_search runs Algorithm 1 (Sec. 3.1.3) for a batch of queries.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are raw pointers to DEVICE memory on the index's device
+ *    unless stated otherwise; the caller owns them.  Row-major layouts.
+ *  - Work is enqueued on the index's stream (qg_set_stream, default: the
+ *    null stream) and the call returns after enqueueing; outputs are valid
+ *    once that stream has reached the call.
+ *  - Return value: QG_OK or a negative QG_E* code.  Argument errors are
+ *    detected before anything is enqueued.  qg_last_error() describes the
+ *    last failure on the calling thread.  No C++ exception crosses the ABI.
+ *  - Distances are squared Euclidean distances in fp32.  Cosine similarity
+ *    is served by searching unit-norm vectors (Sec. 3, footnote on metrics).
+ */
+#ifndef QG_H
+#define QG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qg_index qg_index;
+
+enum {
+  QG_OK = 0,
+  QG_EINVAL = -1,       /* bad argument (NULL pointer, negative size, k or ef <= 0, ...) */
+  QG_ENOMEM = -2,       /* device or host allocation failed */
+  QG_EIO = -3,          /* file could not be opened, read or written */
+  QG_EFORMAT = -4,      /* index file malformed: magic, version, sizes or checksum */
+  QG_EDEVICE = -5,      /* a HIP runtime call failed */
+  QG_EUNSUPPORTED = -6  /* valid but not supported: (D, R) pair, ef or k above the maximum */
+};
+
+/* Flags for qg_search_ex. */
+enum {
+  QG_SEARCH_NO_ME = 1,     /* "w/o ME" ablation (Sec. 4.2.3): a vertex enters the beam only on its first estimate */
+  QG_SEARCH_SMALL_HASH = 2 /* test hook: shrink the on-chip visited set to 128 slots so that queries take the
+                              overflow path (results are identical by construction) */
+};
+
+/* Largest supported beam size and result count. */
+#define QG_MAX_EF 2048
+#define QG_MAX_K 1024
+
+/* Load an index file (4096-byte header, rotation, vertex blocks; FNV-1a-64
+ * checksum verified) into device memory of `device`.  *out receives a new
+ * index, NULL on error.  Supported (D, R): D in {96, 128, 768, 960} (or any
+ * multiple of 32 up to 1024 for which the library was built), R in {32, 64}. */
+int qg_load_index(const char *path, int device, qg_index **out);
+
+/* Build an index on `device` from vectors[n][d] (fp32), graph[n][r] (int32
+ * ids in [0, n), -1 = empty slot), rotation[d][d] (fp32, the matrix M =
+ * P^{-1} applied to vectors, Eq. rotation) and the entry vertex.  All three
+ * arrays are device pointers; they are read during the call and may be freed
+ * afterwards.  Encodes every block on the GPU (Sec. 3.1.1 normalisation by
+ * the holding vertex; Alg. 2 "prepare data for FastScan"). Synchronous. */
+int qg_build_index(const float *vectors, int64_t n, int32_t d, const int32_t *graph, int32_t r,
+                   const float *rotation, int32_t entry, int device, qg_index **out);
+
+/* Write the index to a file in the format read by qg_load_index. Synchronous. */
+int qg_save_index(const qg_index *idx, const char *path);
+
+/* Algorithm 1 for nq queries[nq][d] (fp32): out_ids[nq][k] (int32) and
+ * out_dists[nq][k] (fp32), each row ascending by (distance, id), padded with
+ * (-1, +inf) when fewer than k vertices were visited.  1 <= k <= QG_MAX_K,
+ * 1 <= ef <= QG_MAX_EF (ef is the beam size n_b; it is not raised to k).
+ * nq == 0 is a no-op. */
+int qg_search(const qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t *out_ids,
+              float *out_dists);
+
+/* qg_search with flags (QG_SEARCH_*) and optional per-query counters
+ * out_stats[nq][4] (int32, device, nullable): expansions (vertices whose
+ * exact distance was computed), pops from the beam, appended candidates, and
+ * 1 if the query was finished by the overflow path (its visited set outgrew
+ * on-chip memory; results are identical either way). */
+int qg_search_ex(const qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                 int32_t *out_ids, float *out_dists, int32_t *out_stats);
+
+/* out[n][d] = M in[n][d] for the index's rotation M (Eq. rotation), on the
+ * matrix cores: fp64 products accumulated over j ascending, rounded once to
+ * fp32.  This is the first step of qg_search, exposed for checking. */
+int qg_rotate(const qg_index *idx, const float *in, int64_t n, float *out);
+
+/* The estimator alone (Sec. 3.1.1, Eq. 3.1): for query i and vertex
+ * vertex_of_query[i], out_S[i][r] = FastScan sums S_j (int32),
+ * out_est[i][r] = estimated squared distances of the vertex's neighbours,
+ * out_dist[i] = exact squared distance to the vertex.  Same device code as
+ * qg_search. */
+int qg_estimate(const qg_index *idx, const float *queries, const int32_t *vertex_of_query, int64_t nq,
+                int32_t *out_S, float *out_est, float *out_dist);
+
+/* Copy blocks [first, first + count) (block_bytes each) to device memory dst. */
+int qg_copy_blocks(const qg_index *idx, int64_t first, int64_t count, void *dst);
+
+/* Select the HIP stream (hipStream_t) for later work; NULL = null stream. */
+int qg_set_stream(qg_index *idx, void *hip_stream);
+
+/* Index geometry; any output pointer may be NULL. Host pointers. */
+int qg_index_info(const qg_index *idx, int64_t *n, int32_t *d, int32_t *r, int32_t *entry, int64_t *block_bytes);
+
+/* Kernel timing with HIP events recorded on the index's stream around every
+ * search-kernel launch (kernel 1) and rotation launch (kernel 0).
+ * qg_timing(idx, 1) clears and starts recording, qg_timing(idx, 0) stops.
+ * qg_timing_read waits for the recorded events and returns the number of
+ * launches and their summed duration in milliseconds (host pointers). */
+int qg_timing(qg_index *idx, int enable);
+int qg_timing_read(qg_index *idx, int kernel, int32_t *launches, double *total_ms);
+
+/* Release all device memory of the index. NULL is accepted. */
+void qg_free_index(qg_index *idx);
+
+/* Description of the last error on this thread (empty string if none). */
+const char *qg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QG_H */

@@ -1,0 +1,506 @@
+// qg_api.cpp -- host side of libqg: index lifetime, file I/O, argument checks,
+// scratch management and kernel launches (C ABI declared in include/qg.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qg.h"
+#include "qg_kernels.h"
+#include "qg_layout.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return QG_EDEVICE;
+}
+
+#define HIP_TRY(call, what)                      \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr int kCounters = 4;
+constexpr int kTimingSlots = 4096;
+
+// FNV-1a 64 over a byte range (file checksum).
+uint64_t fnv1a(uint64_t h, const uint8_t* p, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ULL;
+  }
+  return h;
+}
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&old_);
+    if (old_ != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() { (void)hipSetDevice(old_); }
+
+ private:
+  int old_ = 0;
+};
+
+}  // namespace
+
+struct qg_index {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t N = 0;
+  int D = 0, R = 0, entry = 0;
+  int64_t block_bytes = 0;
+  float* rot = nullptr;       // M, [D][D]
+  uint8_t* blocks = nullptr;  // [N][block_bytes]
+  // scratch for searches
+  float* qrot = nullptr;
+  int64_t qrot_cap = 0;  // queries
+  int32_t* overflow = nullptr;
+  int64_t overflow_cap = 0;
+  int* counters = nullptr;
+  uint32_t* fb_bits = nullptr;
+  int fb_slots = 0;
+  int64_t fb_words = 0;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev[2];  // pairs per kernel class
+  int ev_used[2] = {0, 0};
+};
+
+static int validate_shape(int64_t n, int d, int r) {
+  if (n <= 0 || n > 0x7fffffffLL) return fail(QG_EINVAL, "n must be in [1, 2^31)");
+  if (d <= 0 || r <= 0) return fail(QG_EINVAL, "d and r must be positive");
+  if (!qgk::shape_supported(d, r))
+    return fail(QG_EUNSUPPORTED, "unsupported (d, r) = (" + std::to_string(d) + ", " + std::to_string(r) + ")");
+  return QG_OK;
+}
+
+static int alloc_common(qg_index* idx) {
+  HIP_TRY(hipMalloc(&idx->rot, sizeof(float) * idx->D * idx->D), "hipMalloc rotation");
+  HIP_TRY(hipMalloc(&idx->blocks, (size_t)(idx->N * idx->block_bytes)), "hipMalloc blocks");
+  HIP_TRY(hipMalloc(&idx->counters, sizeof(int) * kCounters), "hipMalloc counters");
+  HIP_TRY(hipMemset(idx->counters, 0, sizeof(int) * kCounters), "hipMemset counters");
+  idx->fb_slots = 64;
+  idx->fb_words = (idx->N + 31) / 32;
+  HIP_TRY(hipMalloc(&idx->fb_bits, sizeof(uint32_t) * (size_t)(idx->fb_words * idx->fb_slots)), "hipMalloc bitsets");
+  return QG_OK;
+}
+
+static void release(qg_index* idx) {
+  if (!idx) return;
+  DeviceGuard g(idx->device);
+  (void)hipFree(idx->rot);
+  (void)hipFree(idx->blocks);
+  (void)hipFree(idx->qrot);
+  (void)hipFree(idx->overflow);
+  (void)hipFree(idx->counters);
+  (void)hipFree(idx->fb_bits);
+  for (auto& v : idx->ev)
+    for (auto e : v) (void)hipEventDestroy(e);
+  delete idx;
+}
+
+static int ensure_scratch(qg_index* idx, int64_t nq) {
+  if (nq > idx->qrot_cap) {
+    int64_t cap = std::max<int64_t>(nq, 1024);
+    (void)hipFree(idx->qrot);
+    idx->qrot = nullptr;
+    idx->qrot_cap = 0;
+    HIP_TRY(hipMalloc(&idx->qrot, sizeof(float) * (size_t)(cap * idx->D)), "hipMalloc rotated queries");
+    idx->qrot_cap = cap;
+  }
+  if (nq > idx->overflow_cap) {
+    int64_t cap = std::max<int64_t>(nq, 1024);
+    (void)hipFree(idx->overflow);
+    idx->overflow = nullptr;
+    idx->overflow_cap = 0;
+    HIP_TRY(hipMalloc(&idx->overflow, sizeof(int32_t) * (size_t)cap), "hipMalloc overflow list");
+    idx->overflow_cap = cap;
+  }
+  return QG_OK;
+}
+
+static int record(qg_index* idx, int kind, bool start) {
+  if (!idx->timing) return QG_OK;
+  auto& v = idx->ev[kind];
+  int slot = idx->ev_used[kind];
+  if (start) {
+    if (slot + 2 > kTimingSlots) return QG_OK;  // ring full: stop recording
+    while ((int)v.size() < slot + 2) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+      v.push_back(e);
+    }
+    HIP_TRY(hipEventRecord(v[slot], idx->stream), "hipEventRecord");
+  } else {
+    if (slot + 2 > (int)v.size()) return QG_OK;
+    HIP_TRY(hipEventRecord(v[slot + 1], idx->stream), "hipEventRecord");
+    idx->ev_used[kind] = slot + 2;
+  }
+  return QG_OK;
+}
+
+extern "C" {
+
+const char* qg_last_error(void) { return g_err.c_str(); }
+
+void qg_free_index(qg_index* idx) { release(idx); }
+
+int qg_set_stream(qg_index* idx, void* hip_stream) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  idx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return QG_OK;
+}
+
+int qg_index_info(const qg_index* idx, int64_t* n, int32_t* d, int32_t* r, int32_t* entry, int64_t* block_bytes) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (n) *n = idx->N;
+  if (d) *d = idx->D;
+  if (r) *r = idx->R;
+  if (entry) *entry = idx->entry;
+  if (block_bytes) *block_bytes = idx->block_bytes;
+  return QG_OK;
+}
+
+int qg_build_index(const float* vectors, int64_t n, int32_t d, const int32_t* graph, int32_t r,
+                   const float* rotation, int32_t entry, int device, qg_index** out) {
+  if (!out) return fail(QG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!vectors || !graph || !rotation) return fail(QG_EINVAL, "NULL array");
+  int rc = validate_shape(n, d, r);
+  if (rc) return rc;
+  if (entry < 0 || entry >= n) return fail(QG_EINVAL, "entry out of range");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(QG_EINVAL, "bad device");
+  DeviceGuard g(device);
+  {  // every neighbour id becomes a block address in the kernels: check them all here
+    std::vector<int32_t> h;
+    try {
+      h.resize((size_t)(n * r));
+    } catch (...) {
+      return fail(QG_ENOMEM, "host buffer");
+    }
+    HIP_TRY(hipMemcpy(h.data(), graph, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost), "copy graph");
+    for (int32_t v : h)
+      if (v < -1 || v >= n) return fail(QG_EINVAL, "graph id out of range");
+  }
+  qg_index* idx = new qg_index;
+  idx->device = device;
+  idx->N = n;
+  idx->D = d;
+  idx->R = r;
+  idx->entry = entry;
+  idx->block_bytes = qgl::block_bytes(d, r);
+  if ((rc = alloc_common(idx)) != QG_OK) {
+    release(idx);
+    return rc;
+  }
+  float* tmp = nullptr;
+  hipError_t e = hipMalloc(&tmp, sizeof(float) * (size_t)(n * d));
+  if (e != hipSuccess) {
+    release(idx);
+    return hip_fail(e, "hipMalloc rotated vectors");
+  }
+  e = hipMemcpy(idx->rot, rotation, sizeof(float) * d * d, hipMemcpyDeviceToDevice);
+  if (e == hipSuccess) e = hipMemset(idx->blocks, 0, (size_t)(n * idx->block_bytes));
+  if (e == hipSuccess) e = qgk::launch_rotate(vectors, n, d, idx->rot, tmp, nullptr, 0, nullptr);
+  if (e == hipSuccess) e = qgk::launch_encode(vectors, tmp, n, d, graph, r, idx->blocks, idx->block_bytes, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(tmp);
+  if (e != hipSuccess) {
+    release(idx);
+    return hip_fail(e, "encode");
+  }
+  *out = idx;
+  return QG_OK;
+}
+
+int qg_load_index(const char* path, int device, qg_index** out) {
+  if (!out) return fail(QG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!path) return fail(QG_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(QG_EIO, std::string("cannot open ") + path);
+  uint8_t hdr[4096];
+  if (std::fread(hdr, 1, sizeof hdr, f) != sizeof hdr) {
+    std::fclose(f);
+    return fail(QG_EFORMAT, "truncated header");
+  }
+  auto rd = [&](size_t off, void* dst, size_t n) { std::memcpy(dst, hdr + off, n); };
+  uint32_t ver = 0, hsz = 0;
+  int64_t N = 0, B = 0, off_rot = 0, off_blk = 0;
+  int32_t D = 0, R = 0, entry = 0, qbits = 0;
+  uint64_t payload = 0, cks = 0;
+  rd(8, &ver, 4);
+  rd(12, &hsz, 4);
+  rd(16, &N, 8);
+  rd(24, &D, 4);
+  rd(28, &R, 4);
+  rd(32, &entry, 4);
+  rd(36, &qbits, 4);
+  rd(40, &B, 8);
+  rd(48, &off_rot, 8);
+  rd(56, &off_blk, 8);
+  rd(64, &payload, 8);
+  rd(72, &cks, 8);
+  if (std::memcmp(hdr, "QGINDEX1", 8) != 0 || ver != 1 || hsz != 4096) {
+    std::fclose(f);
+    return fail(QG_EFORMAT, "bad magic or version");
+  }
+  if (D <= 0 || R <= 0 || N <= 0 || qbits != 8 || entry < 0 || entry >= N || B != qgl::block_bytes(D, R) ||
+      off_rot != 4096 || off_blk < off_rot + 4LL * D * D || (uint64_t)(off_blk - 4096) + (uint64_t)(N * B) != payload) {
+    std::fclose(f);
+    return fail(QG_EFORMAT, "inconsistent header fields");
+  }
+  int rc = validate_shape(N, D, R);
+  if (rc) {
+    std::fclose(f);
+    return rc;
+  }
+  std::vector<uint8_t> buf;
+  try {
+    buf.resize(payload);
+  } catch (...) {
+    std::fclose(f);
+    return fail(QG_ENOMEM, "host buffer");
+  }
+  size_t got = std::fread(buf.data(), 1, payload, f);
+  uint8_t extra;
+  bool trailing = std::fread(&extra, 1, 1, f) == 1;
+  std::fclose(f);
+  if (got != payload || trailing) return fail(QG_EFORMAT, "file size does not match header");
+  if (fnv1a(0xcbf29ce484222325ULL, buf.data(), buf.size()) != cks) return fail(QG_EFORMAT, "checksum mismatch");
+  {  // neighbour ids become block addresses in the kernels: all must be -1 or in [0, N)
+    const uint8_t* blk0 = buf.data() + (off_blk - 4096);
+    for (int64_t v = 0; v < N; ++v) {
+      const int32_t* nb = reinterpret_cast<const int32_t*>(blk0 + v * B + qgl::off_nbr(D, R));
+      for (int j = 0; j < R; ++j) {
+        int32_t x;
+        std::memcpy(&x, nb + j, 4);
+        if (x < -1 || x >= N) return fail(QG_EFORMAT, "neighbour id out of range");
+      }
+    }
+  }
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(QG_EINVAL, "bad device");
+  DeviceGuard g(device);
+  qg_index* idx = new qg_index;
+  idx->device = device;
+  idx->N = N;
+  idx->D = D;
+  idx->R = R;
+  idx->entry = entry;
+  idx->block_bytes = B;
+  if ((rc = alloc_common(idx)) != QG_OK) {
+    release(idx);
+    return rc;
+  }
+  hipError_t e = hipMemcpy(idx->rot, buf.data(), sizeof(float) * D * D, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(idx->blocks, buf.data() + (off_blk - 4096), (size_t)(N * B), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    release(idx);
+    return hip_fail(e, "upload index");
+  }
+  *out = idx;
+  return QG_OK;
+}
+
+int qg_save_index(const qg_index* idx, const char* path) {
+  if (!idx || !path) return fail(QG_EINVAL, "NULL argument");
+  DeviceGuard g(idx->device);
+  const int64_t rot_bytes = 4LL * idx->D * idx->D, rot_pad = (rot_bytes + 4095) / 4096 * 4096;
+  const int64_t payload = rot_pad + idx->N * idx->block_bytes;
+  std::vector<uint8_t> buf;
+  try {
+    buf.assign(payload, 0);
+  } catch (...) {
+    return fail(QG_ENOMEM, "host buffer");
+  }
+  HIP_TRY(hipStreamSynchronize(idx->stream), "hipStreamSynchronize");
+  HIP_TRY(hipMemcpy(buf.data(), idx->rot, rot_bytes, hipMemcpyDeviceToHost), "download rotation");
+  HIP_TRY(hipMemcpy(buf.data() + rot_pad, idx->blocks, (size_t)(idx->N * idx->block_bytes), hipMemcpyDeviceToHost),
+          "download blocks");
+  uint8_t hdr[4096];
+  std::memset(hdr, 0, sizeof hdr);
+  std::memcpy(hdr, "QGINDEX1", 8);
+  const uint32_t ver = 1, hsz = 4096;
+  const int32_t qbits = 8;
+  const int64_t off_rot = 4096, off_blk = 4096 + rot_pad;
+  const uint64_t cks = fnv1a(0xcbf29ce484222325ULL, buf.data(), buf.size());
+  auto wr = [&](size_t off, const void* src, size_t n) { std::memcpy(hdr + off, src, n); };
+  wr(8, &ver, 4);
+  wr(12, &hsz, 4);
+  wr(16, &idx->N, 8);
+  wr(24, &idx->D, 4);
+  wr(28, &idx->R, 4);
+  wr(32, &idx->entry, 4);
+  wr(36, &qbits, 4);
+  wr(40, &idx->block_bytes, 8);
+  wr(48, &off_rot, 8);
+  wr(56, &off_blk, 8);
+  wr(64, &payload, 8);
+  wr(72, &cks, 8);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(QG_EIO, std::string("cannot create ") + path);
+  bool ok = std::fwrite(hdr, 1, sizeof hdr, f) == sizeof hdr && std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? QG_OK : fail(QG_EIO, "write failed");
+}
+
+int qg_rotate(const qg_index* idx, const float* in, int64_t n, float* out) {
+  if (!idx || (n > 0 && (!in || !out))) return fail(QG_EINVAL, "NULL argument");
+  if (n < 0) return fail(QG_EINVAL, "n < 0");
+  if (n == 0) return QG_OK;
+  DeviceGuard g(idx->device);
+  HIP_TRY(qgk::launch_rotate(in, n, idx->D, idx->rot, out, nullptr, 0, idx->stream), "rotate");
+  return QG_OK;
+}
+
+int qg_search_ex(const qg_index* cidx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                 int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+  qg_index* idx = const_cast<qg_index*>(cidx);
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (nq < 0) return fail(QG_EINVAL, "nq < 0");
+  if (k <= 0 || ef <= 0) return fail(QG_EINVAL, "k and ef must be positive");
+  if (k > QG_MAX_K || ef > QG_MAX_EF) return fail(QG_EUNSUPPORTED, "k or ef above the supported maximum");
+  if (flags & ~(QG_SEARCH_NO_ME | QG_SEARCH_SMALL_HASH)) return fail(QG_EINVAL, "unknown flags");
+  if (flags & QG_SEARCH_NO_ME) return fail(QG_EUNSUPPORTED, "QG_SEARCH_NO_ME is not supported on the device");
+  if (nq == 0) return QG_OK;
+  if (nq > 0x7fffffffLL) return fail(QG_EINVAL, "nq too large");
+  if (!queries || !out_ids || !out_dists) return fail(QG_EINVAL, "NULL array");
+  DeviceGuard g(idx->device);
+  int rc = ensure_scratch(idx, nq);
+  if (rc) return rc;
+
+  const int ef_cap = (ef + 63) / 64 * 64;
+  const int k_cap = (k + 63) / 64 * 64;
+  // visited hash: room for about 8 ef ids at load <= 1/2, at least 128 slots
+  int hbits = 7;
+  while ((1 << hbits) < 8 * ef && hbits < 14 && !(flags & QG_SEARCH_SMALL_HASH)) ++hbits;
+  qgk::SearchArgs a{};
+  a.blocks = idx->blocks;
+  a.block_bytes = idx->block_bytes;
+  a.N = idx->N;
+  a.queries = queries;
+  a.qrot = idx->qrot;
+  a.nq = nq;
+  a.k = k;
+  a.ef = ef;
+  a.k_cap = k_cap;
+  a.ef_cap = ef_cap;
+  a.hash_bits = hbits;
+  a.flags = flags;
+  a.entry = idx->entry;
+  a.out_ids = out_ids;
+  a.out_dists = out_dists;
+  a.out_stats = out_stats;
+  a.counters = idx->counters;
+  a.overflow_list = idx->overflow;
+  a.fb_bits = idx->fb_bits;
+  a.fb_words = idx->fb_words;
+
+  const qgl::SearchLds L = qgl::search_lds(idx->D, idx->R, ef_cap, 1 << hbits, k_cap);
+  const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
+  const size_t lds_cap = 160 * 1024;
+  int wpb = 4;
+  while (wpb > 1 && (size_t)wpb * L.total > lds_cap) wpb >>= 1;
+  if ((size_t)L.total > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
+  int occ = qgk::search_occupancy(idx->D, idx->R, false, wpb, (size_t)wpb * L.total);
+  if (occ <= 0) occ = 1;
+  int64_t want = (nq + wpb - 1) / wpb;
+  int grid = (int)std::min<int64_t>(want, (int64_t)occ * 256);
+
+  if ((rc = record(idx, 0, true))) return rc;
+  HIP_TRY(qgk::launch_rotate(queries, nq, idx->D, idx->rot, idx->qrot, idx->counters, kCounters, idx->stream),
+          "rotate queries");
+  if ((rc = record(idx, 0, false))) return rc;
+  if ((rc = record(idx, 1, true))) return rc;
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, a, grid, wpb, (size_t)wpb * L.total, idx->stream), "search");
+  if ((rc = record(idx, 1, false))) return rc;
+  // overflow pass: one wavefront per workgroup, one bitset each
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, a, idx->fb_slots, 1, (size_t)Lf.total, idx->stream),
+          "search overflow pass");
+  return QG_OK;
+}
+
+int qg_search(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t* out_ids,
+              float* out_dists) {
+  return qg_search_ex(idx, queries, nq, k, ef, 0, out_ids, out_dists, nullptr);
+}
+
+int qg_estimate(const qg_index* cidx, const float* queries, const int32_t* vertex_of_query, int64_t nq,
+                int32_t* out_S, float* out_est, float* out_dist) {
+  qg_index* idx = const_cast<qg_index*>(cidx);
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (nq < 0) return fail(QG_EINVAL, "nq < 0");
+  if (nq == 0) return QG_OK;
+  if (!queries || !vertex_of_query || !out_S || !out_est || !out_dist) return fail(QG_EINVAL, "NULL array");
+  DeviceGuard g(idx->device);
+  int rc = ensure_scratch(idx, nq);
+  if (rc) return rc;
+  // vertex ids are checked on the host copy to keep every block access in bounds
+  std::vector<int32_t> v((size_t)nq);
+  HIP_TRY(hipMemcpyAsync(v.data(), vertex_of_query, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, idx->stream),
+          "copy vertex ids");
+  HIP_TRY(hipStreamSynchronize(idx->stream), "hipStreamSynchronize");
+  for (int32_t x : v)
+    if (x < 0 || x >= idx->N) return fail(QG_EINVAL, "vertex id out of range");
+  HIP_TRY(qgk::launch_rotate(queries, nq, idx->D, idx->rot, idx->qrot, nullptr, 0, idx->stream), "rotate");
+  qgk::EstimateArgs a{idx->blocks, idx->block_bytes, queries, idx->qrot, vertex_of_query, out_S, out_est, out_dist};
+  HIP_TRY(qgk::launch_estimate(idx->D, idx->R, a, nq, idx->stream), "estimate");
+  return QG_OK;
+}
+
+int qg_copy_blocks(const qg_index* idx, int64_t first, int64_t count, void* dst) {
+  if (!idx || !dst) return fail(QG_EINVAL, "NULL argument");
+  if (first < 0 || count < 0 || first + count > idx->N) return fail(QG_EINVAL, "block range out of bounds");
+  if (count == 0) return QG_OK;
+  DeviceGuard g(idx->device);
+  HIP_TRY(hipMemcpyAsync(dst, idx->blocks + first * idx->block_bytes, (size_t)(count * idx->block_bytes),
+                         hipMemcpyDeviceToDevice, idx->stream),
+          "copy blocks");
+  return QG_OK;
+}
+
+int qg_timing(qg_index* idx, int enable) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  idx->timing = enable != 0;
+  if (enable) idx->ev_used[0] = idx->ev_used[1] = 0;
+  return QG_OK;
+}
+
+int qg_timing_read(qg_index* idx, int kernel, int32_t* launches, double* total_ms) {
+  if (!idx || !launches || !total_ms || kernel < 0 || kernel > 1) return fail(QG_EINVAL, "bad argument");
+  DeviceGuard g(idx->device);
+  double tot = 0.0;
+  const int used = idx->ev_used[kernel];
+  for (int i = 0; i + 1 < used; i += 2) {
+    HIP_TRY(hipEventSynchronize(idx->ev[kernel][i + 1]), "hipEventSynchronize");
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, idx->ev[kernel][i], idx->ev[kernel][i + 1]), "hipEventElapsedTime");
+    tot += ms;
+  }
+  *launches = used / 2;
+  *total_ms = tot;
+  return QG_OK;
+}
+
+}  // extern "C"

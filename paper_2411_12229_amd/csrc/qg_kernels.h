@@ -1,0 +1,49 @@
+// qg_kernels.h -- launch interface between the libqg host code and its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qgk {
+
+struct SearchArgs {
+  const uint8_t* blocks;
+  int64_t block_bytes;
+  int64_t N;
+  const float* queries;  // [nq][D] raw queries
+  const float* qrot;     // [nq][D] rotated queries
+  int64_t nq;
+  int k, ef, k_cap, ef_cap;
+  int hash_bits;  // LDS visited hash holds 2^hash_bits ids
+  int flags;
+  int entry;
+  int32_t* out_ids;
+  float* out_dists;
+  int32_t* out_stats;     // nullable, [nq][4]
+  int* counters;          // [0] main queue, [1] overflow count, [2] overflow queue
+  int32_t* overflow_list; // [nq]
+  uint32_t* fb_bits;      // overflow pass: one N-bit set per wavefront
+  int64_t fb_words;       // 32-bit words per set
+};
+
+struct EstimateArgs {
+  const uint8_t* blocks;
+  int64_t block_bytes;
+  const float* queries;
+  const float* qrot;
+  const int32_t* vertex;
+  int32_t* out_S;
+  float* out_est;
+  float* out_dist;
+};
+
+bool shape_supported(int D, int R);
+hipError_t launch_rotate(const float* in, int64_t n, int D, const float* M, float* out, int* zero, int nzero,
+                         hipStream_t st);
+hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, const int32_t* G, int R,
+                         uint8_t* blocks, int64_t B, hipStream_t st);
+hipError_t launch_search(int D, int R, bool overflow_pass, const SearchArgs& a, int grid, int wpb, size_t lds,
+                         hipStream_t st);
+int search_occupancy(int D, int R, bool overflow_pass, int wpb, size_t lds);
+hipError_t launch_estimate(int D, int R, const EstimateArgs& a, int64_t nq, hipStream_t st);
+
+}  // namespace qgk

@@ -1,0 +1,674 @@
+// qg_kernels.hip -- gfx950 kernels of the SymphonyQG query path.
+//
+//  rotate_kernel  : Y = X M^T on the matrix cores (fp64 MFMA 16x16x4, k ascending).
+//  encode_kernel  : RaBitQ codes and factors of every edge, one wavefront per vertex.
+//  search_kernel  : Algorithm 1, one query per wavefront; LUT, beam, visited
+//                   hash and top-k live in LDS, vertex blocks stream from HBM.
+//  estimate_kernel: the estimator alone for (query, vertex) pairs.
+//
+// Compiled with -ffp-contract=off: every fused multiply-add below is explicit.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qg_kernels.h"
+#include "qg_layout.h"
+
+namespace qgk {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kChecked = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7fffffffu;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+// (key, id) lexicographic order.
+__device__ __forceinline__ bool kv_less(float ka, uint32_t ia, float kb, uint32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int s = 32; s >= 1; s >>= 1) v = fmaxf(v, __shfl_xor(v, s, 64));
+  return v;
+}
+
+// Exact squared distance |q - x|^2 (implicit re-ranking, Sec. 3.1.2): dim i
+// into lane i mod 64 by a fused multiply-add chain in ascending i, then the
+// xor butterfly p[l] + p[l^s], s = 32 ... 1.  Every lane ends with the result.
+template <int DPL>
+__device__ __forceinline__ float exact_dist(const float (&qv)[DPL], const float (&xv)[DPL]) {
+  float p = 0.0f;
+#pragma unroll
+  for (int t = 0; t < DPL; ++t) {
+    float d = qv[t] - xv[t];
+    p = __builtin_fmaf(d, d, p);
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) p = p + __shfl_xor(p, s, 64);
+  return p;
+}
+
+// ---------------------------------------------------------------- rotation
+
+// out[r][i] = fl32(sum_j M[i][j] in[r][j]), fp64 products accumulated over j
+// ascending (each 16x16x4 MFMA applies its four k terms in order as fused
+// multiply-adds onto the accumulator), one 16x16 output tile per wavefront.
+// Block (0,0) also clears `nzero` ints at `zero` for the kernels that follow.
+__global__ __launch_bounds__(64) void rotate_kernel(const float* __restrict__ in, int64_t n, int D,
+                                                    const float* __restrict__ M, float* __restrict__ out,
+                                                    int* __restrict__ zero, int nzero) {
+  const int lane = threadIdx.x;
+  if (zero && blockIdx.x == 0 && blockIdx.y == 0 && lane < nzero) zero[lane] = 0;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  const int i0 = blockIdx.y * 16;
+  const int64_t ra = r0 + (lane & 15);
+  const int kk = lane >> 4;
+  const float* arow = in + (ra < n ? ra : 0) * (int64_t)D;
+  const float* brow = M + (int64_t)(i0 + (lane & 15)) * D;
+  const bool rok = ra < n;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int kb = 0; kb < D; kb += 4) {
+    double a = rok ? (double)arow[kb + kk] : 0.0;
+    double b = (double)brow[kb + kk];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    int64_t rr = r0 + (lane >> 4) + 4 * v;
+    if (rr < n) out[rr * D + i0 + (lane & 15)] = (float)acc[v];
+  }
+}
+
+// ------------------------------------------------------------------ encode
+
+__device__ __forceinline__ double butterfly_d(double p) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) p = p + __shfl_xor(p, s, 64);
+  return p;
+}
+
+// One wavefront per holder vertex c.  For every edge c -> o (Sec. 3.1.1,
+// centre = c): y = rot(o) - rot(c) in fp32, bit i = [y_i > 0]; fp64 sums
+// |r|^2, sum |y_i| and xc = sum (2b_i - 1) rot(c)_i with dim i in lane i mod
+// 64 and a butterfly; f_rescale = -2|r|^2 / sum|y|, f_add = |r|^2 - f_rescale*xc
+// (Eq. normalization with Eq. 3.1; degenerate edge: f_rescale = 0,
+// f_add = |r|^2).  The block buffer must be zeroed beforehand.
+__global__ __launch_bounds__(256) void encode_kernel(const float* __restrict__ X, const float* __restrict__ ROT,
+                                                     int64_t N, int D, const int32_t* __restrict__ G, int R,
+                                                     uint8_t* __restrict__ blocks, int64_t B) {
+  const int lane = lane_id();
+  const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (c >= N) return;
+  const int DPL = (D + 63) >> 6;
+  uint8_t* blk = blocks + c * B;
+  const float* xc = X + c * D;
+  const float* rc = ROT + c * D;
+  for (int i = lane; i < D; i += 64) reinterpret_cast<float*>(blk)[i] = xc[i];
+  uint8_t* codes = blk + qgl::off_codes(D);
+  float* fadd = reinterpret_cast<float*>(blk + qgl::off_fadd(D, R));
+  float* fres = reinterpret_cast<float*>(blk + qgl::off_fres(D, R));
+  int32_t* nbr = reinterpret_cast<int32_t*>(blk + qgl::off_nbr(D, R));
+  for (int j = 0; j < R; ++j) {
+    const int32_t o = G[c * R + j];
+    if (o < 0) {
+      if (lane == 0) {
+        fadd[j] = 0.0f;
+        fres[j] = 0.0f;
+        nbr[j] = -1;
+      }
+      continue;
+    }
+    const float* xo = X + (int64_t)o * D;
+    const float* ro = ROT + (int64_t)o * D;
+    double pr = 0.0, pa = 0.0, px = 0.0;
+    uint8_t* code = codes + (int64_t)j * (D / 8);
+    for (int t = 0; t < DPL; ++t) {
+      const int i = lane + 64 * t;
+      bool bit = false;
+      if (i < D) {
+        double d = (double)xo[i] - (double)xc[i];
+        pr = __builtin_fma(d, d, pr);
+        float y = ro[i] - rc[i];
+        bit = y > 0.0f;
+        pa = pa + __builtin_fabs((double)y);
+        px = bit ? px + (double)rc[i] : px - (double)rc[i];
+      }
+      uint64_t m = ballot(bit);
+      const int nbytes = (D - 64 * t) >= 64 ? 8 : (D - 64 * t) / 8;
+      if (lane < nbytes) code[8 * t + lane] = (uint8_t)(m >> (8 * lane));
+    }
+    pr = butterfly_d(pr);
+    pa = butterfly_d(pa);
+    px = butterfly_d(px);
+    if (lane == 0) {
+      if (pa == 0.0) {
+        fres[j] = 0.0f;
+        fadd[j] = (float)pr;
+      } else {
+        double fr = (-2.0 * pr) / pa;
+        double fa = pr - fr * px;
+        fres[j] = (float)fr;
+        fadd[j] = (float)fa;
+      }
+      nbr[j] = o;
+    }
+  }
+}
+
+// ------------------------------------------------------------- query side
+
+// Per-query quantisation and LUT (Sec. 2.2 FastScan with the query-only LUT
+// of Eq. 3.1b): m = max|q'_i|, inv = fl32(127/m), q_s = clamp(rint(q'_i*inv)),
+// Delta = fl32(m/127); LUT[k][p] = sum_t (bit t of p ? q_s[4k+t] : -q_s[4k+t]),
+// stored as int16 rows of 16, with one padding row before the second lane
+// group's rows when two lanes share a neighbour.  Returns Delta.
+template <int D, int R>
+__device__ __forceinline__ float build_lut(const float* __restrict__ qrot, int16_t* lut) {
+  constexpr int ROWS = D / 4;
+  constexpr int RPG = D / 4 / (64 / R);
+  const int lane = lane_id();
+  float m = 0.0f;
+  for (int i = lane; i < D; i += 64) m = fmaxf(m, __builtin_fabsf(qrot[i]));
+  m = wave_max(m);
+  float inv = 0.0f, delta = 0.0f;
+  if (m != 0.0f) {
+    inv = 127.0f / m;
+    delta = m / 127.0f;
+  }
+  for (int w = lane; w < 2 * ROWS; w += 64) {
+    const int k = w >> 1, half = w & 1;
+    int s[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float v = (m != 0.0f) ? __builtin_rintf(qrot[4 * k + t] * inv) : 0.0f;
+      v = fminf(fmaxf(v, -127.0f), 127.0f);
+      s[t] = (int)v;
+    }
+    int16_t* row = lut + (k + k / RPG) * 16;
+#pragma unroll
+    for (int pp = 0; pp < 8; ++pp) {
+      const int p = half * 8 + pp;
+      int acc = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc += ((p >> t) & 1) ? s[t] : -s[t];
+      row[p] = (int16_t)acc;
+    }
+  }
+  wave_sync();
+  return delta;
+}
+
+// Vertex block fields as one lane sees them: its dims of the raw vector, its
+// share of one neighbour's code, that neighbour's factors and id.
+template <int D, int R>
+struct BlockView {
+  static constexpr int LPN = 64 / R;        // lanes per neighbour
+  static constexpr int CB = D / 8;          // code bytes per neighbour
+  static constexpr int BPL = CB / LPN;      // code bytes per lane
+  static constexpr int DPL = (D + 63) / 64; // raw dims per lane
+  static constexpr bool WORDS = (BPL % 4) == 0;
+  static constexpr int NW = WORDS ? BPL / 4 : BPL / 2;  // 32- or 16-bit code units per lane
+  float x[DPL];
+  uint32_t cw[NW];
+  float fa, fr;
+  int32_t nb;
+
+  __device__ __forceinline__ void load(const uint8_t* __restrict__ blk, int lane) {
+    const float* raw = reinterpret_cast<const float*>(blk);
+#pragma unroll
+    for (int t = 0; t < DPL; ++t) {
+      const int i = lane + 64 * t;
+      x[t] = (i < D) ? raw[i] : 0.0f;
+    }
+    const int j = lane / LPN, h = lane % LPN;
+    const uint8_t* cp = blk + qgl::off_codes(D) + j * CB + h * BPL;
+    if constexpr (WORDS) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) cw[w] = reinterpret_cast<const uint32_t*>(cp)[w];
+    } else {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) cw[w] = reinterpret_cast<const uint16_t*>(cp)[w];
+    }
+    fa = reinterpret_cast<const float*>(blk + qgl::off_fadd(D, R))[j];
+    fr = reinterpret_cast<const float*>(blk + qgl::off_fres(D, R))[j];
+    nb = reinterpret_cast<const int32_t*>(blk + qgl::off_nbr(D, R))[j];
+  }
+
+  // FastScan sum of this lane's nibbles; the LPN lanes of one neighbour are
+  // then combined (integer, exact) so every lane holds S_j.
+  __device__ __forceinline__ int fastscan(const int16_t* lut, int lane) const {
+    constexpr int RPG = D / 4 / LPN;
+    constexpr int UNIT_NIB = WORDS ? 8 : 4;
+    const int h = lane % LPN;
+    const int16_t* base = lut + (h * RPG + h) * 16;  // group h starts after h padding rows
+    int s = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+#pragma unroll
+      for (int t = 0; t < UNIT_NIB; ++t) {
+        const int row = w * UNIT_NIB + t;
+        s += base[row * 16 + ((cw[w] >> (4 * t)) & 15u)];
+      }
+    }
+    if constexpr (LPN == 2) s += __shfl_xor(s, 1, 64);
+    return s;
+  }
+};
+
+// ------------------------------------------------------------------ search
+
+struct Visited {
+  // LDS hash (open addressing, linear probing) or, in the overflow path, a
+  // global bitset of N bits private to this wavefront.
+  uint32_t* tab;
+  uint32_t mask;
+  int hbits;
+  uint32_t* bits;
+
+  __device__ __forceinline__ uint32_t slot0(uint32_t id) const {
+    return (id * 0x9E3779B1u) >> (32 - hbits);
+  }
+};
+
+template <bool GV>
+__device__ __forceinline__ bool visited_contains(const Visited& v, uint32_t id) {
+  if constexpr (GV) {
+    uint32_t w = __hip_atomic_load(v.bits + (id >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (w >> (id & 31)) & 1u;
+  } else {
+    uint32_t s = v.slot0(id);
+    for (;;) {
+      uint32_t e = v.tab[s];
+      if (e == id) return true;
+      if (e == kEmpty) return false;
+      s = (s + 1) & v.mask;
+    }
+  }
+}
+
+// Insert id (wave-uniform); returns true if it was already present.
+template <bool GV>
+__device__ __forceinline__ bool visited_insert(const Visited& v, uint32_t id, int lane) {
+  if constexpr (GV) {
+    uint32_t old = 0;
+    if (lane == 0) old = atomicOr(v.bits + (id >> 5), 1u << (id & 31));
+    old = __shfl(old, 0, 64);
+    return (old >> (id & 31)) & 1u;
+  } else {
+    uint32_t base = v.slot0(id);
+    for (;;) {
+      const uint32_t s = (base + lane) & v.mask;
+      const uint32_t e = v.tab[s];
+      const uint64_t fm = ballot(e == id), em = ballot(e == kEmpty);
+      if (fm | em) {
+        const int ff = fm ? first_lane(fm) : 64, fe = em ? first_lane(em) : 64;
+        if (ff < fe) return true;
+        if (lane == fe) v.tab[s] = id;
+        wave_sync();
+        return false;
+      }
+      base += 64;
+    }
+  }
+}
+
+template <int D, int R, bool GV>
+__device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L, uint32_t* gbits) {
+  using BV = BlockView<D, R>;
+  constexpr int DPL = BV::DPL;
+  constexpr int LPN = BV::LPN;
+  const int lane = lane_id();
+  const int ef = a.ef, k = a.k;
+  int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
+  float* bkey = reinterpret_cast<float*>(lds + L.bkey);
+  uint32_t* bid = reinterpret_cast<uint32_t*>(lds + L.bid);
+  float* tkey = reinterpret_cast<float*>(lds + L.tkey);
+  uint32_t* tid = reinterpret_cast<uint32_t*>(lds + L.tid);
+  float* ckey = reinterpret_cast<float*>(lds + L.ckey);
+  uint32_t* cid = reinterpret_cast<uint32_t*>(lds + L.cid);
+  float* nkey = reinterpret_cast<float*>(lds + L.nkey);
+  uint32_t* nid = reinterpret_cast<uint32_t*>(lds + L.nid);
+
+  Visited vis;
+  vis.tab = reinterpret_cast<uint32_t*>(lds + L.hash);
+  vis.hbits = a.hash_bits;
+  vis.mask = (1u << a.hash_bits) - 1u;
+  vis.bits = gbits;
+  int nvis = 0;
+  const int vis_limit = GV ? 0x7fffffff : (1 << a.hash_bits) / 2;
+  if constexpr (GV) {
+    for (int64_t w = lane; w < a.fb_words; w += 64)
+      __hip_atomic_store(gbits + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  } else {
+    for (int i = lane; i < (1 << a.hash_bits); i += 64) vis.tab[i] = kEmpty;
+  }
+
+  float qv[DPL];
+  const float* qr = a.queries + q * D;
+#pragma unroll
+  for (int t = 0; t < DPL; ++t) {
+    const int i = lane + 64 * t;
+    qv[t] = (i < D) ? qr[i] : 0.0f;
+  }
+  const float delta = build_lut<D, R>(a.qrot + q * D, lut);
+
+  // S starts with the entry keyed by its exact distance (reading S13).
+  {
+    BV e;
+    e.load(a.blocks + (int64_t)a.entry * a.block_bytes, lane);
+    const float de = exact_dist<DPL>(qv, e.x);
+    if (lane == 0) {
+      bkey[0] = de;
+      bid[0] = (uint32_t)a.entry;
+    }
+    wave_sync();
+  }
+  int size = 1, cursor = 0, nnc = 0;
+  int expansions = 0, pops = 0, appended = 0;
+
+  for (;;) {
+    // pop the first unchecked entry (the beam is kept sorted by (key, id))
+    int c = -1;
+    while (cursor < size) {
+      const int i = cursor + lane;
+      const bool un = (i < size) && !(bid[i < size ? i : 0] & kChecked);
+      const uint64_t m = ballot(un);
+      if (m) {
+        c = cursor + first_lane(m);
+        break;
+      }
+      cursor += 64;
+    }
+    if (c < 0) break;
+    const uint32_t p = bid[c];
+    wave_sync();
+    if (lane == 0) bid[c] = p | kChecked;
+    wave_sync();
+    cursor = c + 1;
+    ++pops;
+    if (visited_insert<GV>(vis, p, lane)) continue;  // a second estimate of a visited vertex
+    if (++nvis > vis_limit) {  // on-chip visited set full: hand the query to the overflow path
+      if (lane == 0) {
+        const int slot = atomicAdd(a.counters + 1, 1);
+        a.overflow_list[slot] = (int32_t)q;
+      }
+      return;
+    }
+    ++expansions;
+
+    BV b;
+    b.load(a.blocks + (int64_t)p * a.block_bytes, lane);
+    const float dp = exact_dist<DPL>(qv, b.x);
+
+    // implicit re-ranking: NN keeps the k smallest (distance, id) seen
+    if (nnc < k || kv_less(dp, p, nkey[nnc - 1], nid[nnc - 1])) {
+      int pos = 0;
+      for (int base = 0; base < nnc; base += 64) {
+        const int i = base + lane;
+        const bool lt = (i < nnc) && kv_less(nkey[i < nnc ? i : 0], nid[i < nnc ? i : 0], dp, p);
+        pos += __popcll(ballot(lt));
+      }
+      const int last = nnc < k ? nnc : k - 1;  // entries [pos, last) move up by one
+      for (int base = ((last - 1) >> 6) << 6; base >= 0 && last > pos; base -= 64) {
+        const int i = base + lane;
+        float kk = 0.0f;
+        uint32_t ii = 0;
+        const bool mv = (i >= pos) && (i < last);
+        if (mv) {
+          kk = nkey[i];
+          ii = nid[i];
+        }
+        wave_sync();
+        if (mv) {
+          nkey[i + 1] = kk;
+          nid[i + 1] = ii;
+        }
+        wave_sync();
+        if (base < pos) break;
+      }
+      if (lane == 0) {
+        nkey[pos] = dp;
+        nid[pos] = p;
+      }
+      wave_sync();
+      nnc = nnc < k ? nnc + 1 : k;
+    }
+
+    // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
+    const int S = b.fastscan(lut, lane);
+    const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
+    const uint32_t nb = (uint32_t)b.nb;
+    bool valid = (lane % LPN == 0) && b.nb >= 0;
+    if (valid) valid = !visited_contains<GV>(vis, nb);
+    appended += __popcll(ballot(valid));
+    if (size == ef && valid) valid = kv_less(est, nb, bkey[ef - 1], bid[ef - 1] & kIdMask);
+    const uint64_t V = ballot(valid);
+    const int nv = __popcll(V);
+    if (nv == 0) continue;
+
+    // order the candidates by (estimate, id)
+    const int r = lanes_below(V);
+    if (valid) {
+      tkey[r] = est;
+      tid[r] = nb;
+    }
+    wave_sync();
+    int sidx = 0;
+    if (valid)
+      for (int t = 0; t < nv; ++t) sidx += kv_less(tkey[t], tid[t], est, nb);
+    int lb = 0;  // old entries placed before this candidate: those <= it
+    if (valid) {
+      int lo = 0, hi = size;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (!kv_less(est, nb, bkey[mid], bid[mid] & kIdMask))
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      lb = lo;
+      ckey[sidx] = est;
+      cid[sidx] = nb;
+    }
+    wave_sync();
+    // move old entries up by the number of candidates strictly before them,
+    // top chunk first so nothing is overwritten before it is read
+    for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {
+      const int i = base + lane;
+      float kk = 0.0f;
+      uint32_t ii = 0;
+      int np = ef;
+      if (i < size) {
+        kk = bkey[i];
+        ii = bid[i];
+        int lo = 0, hi = nv;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (kv_less(ckey[mid], cid[mid], kk, ii & kIdMask))
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        np = i + lo;
+      }
+      wave_sync();
+      if (np < ef) {
+        bkey[np] = kk;
+        bid[np] = ii;
+      }
+      wave_sync();
+    }
+    const int npos = sidx + lb;
+    if (valid && npos < ef) {
+      bkey[npos] = est;
+      bid[npos] = nb;
+    }
+    wave_sync();
+    const int first = __shfl(npos, first_lane(ballot(valid && sidx == 0)), 64);
+    if (first < cursor) cursor = first;
+    size = (size + nv < ef) ? size + nv : ef;
+  }
+
+  // answer: NN ascending by (distance, id), padded with (-1, inf)
+  for (int i = lane; i < k; i += 64) {
+    a.out_ids[q * k + i] = i < nnc ? (int32_t)nid[i] : -1;
+    a.out_dists[q * k + i] = i < nnc ? nkey[i] : __builtin_inff();
+  }
+  if (a.out_stats && lane == 0) {
+    int32_t* st = a.out_stats + 4 * q;
+    st[0] = expansions;
+    st[1] = pops;
+    st[2] = appended;
+    st[3] = GV ? 1 : 0;
+  }
+}
+
+// Each wavefront takes queries from a shared counter until none is left.
+// GV = false: main pass over all queries with the LDS visited hash.
+// GV = true : overflow pass over the queries the main pass handed over, with
+//             a global bitset per wavefront.
+template <int D, int R, bool GV>
+__global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const qgl::SearchLds L = qgl::search_lds(D, R, a.ef_cap, GV ? 0 : (1 << a.hash_bits), a.k_cap);
+  uint8_t* lds = smem + wave * L.total;
+  const int wid = blockIdx.x * (blockDim.x >> 6) + wave;
+  uint32_t* gbits = GV ? a.fb_bits + (int64_t)wid * a.fb_words : nullptr;
+  int* ctr = a.counters + (GV ? 2 : 0);
+  const int64_t limit = GV ? (int64_t)__hip_atomic_load(a.counters + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : a.nq;
+  for (;;) {
+    int qi = 0;
+    if (lane == 0) qi = atomicAdd(ctr, 1);
+    qi = __shfl(qi, 0, 64);
+    if (qi >= limit) break;
+    const int64_t q = GV ? (int64_t)a.overflow_list[qi] : (int64_t)qi;
+    search_one<D, R, GV>(a, q, lds, L, gbits);
+  }
+}
+
+// -------------------------------------------------------------- estimator
+
+template <int D, int R>
+__global__ __launch_bounds__(64) void estimate_kernel(EstimateArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  using BV = BlockView<D, R>;
+  const int lane = lane_id();
+  const int64_t q = blockIdx.x;
+  int16_t* lut = reinterpret_cast<int16_t*>(smem);
+  const float delta = build_lut<D, R>(a.qrot + q * D, lut);
+  float qv[BV::DPL];
+  for (int t = 0; t < BV::DPL; ++t) {
+    const int i = lane + 64 * t;
+    qv[t] = (i < D) ? a.queries[q * D + i] : 0.0f;
+  }
+  BV b;
+  b.load(a.blocks + (int64_t)a.vertex[q] * a.block_bytes, lane);
+  const float dp = exact_dist<BV::DPL>(qv, b.x);
+  const int S = b.fastscan(lut, lane);
+  const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
+  if (lane % BV::LPN == 0) {
+    a.out_S[q * R + lane / BV::LPN] = S;
+    a.out_est[q * R + lane / BV::LPN] = est;
+  }
+  if (lane == 0) a.out_dist[q] = dp;
+}
+
+// --------------------------------------------------------------- launchers
+
+#define QG_SHAPES(X) X(96, 32) X(96, 64) X(128, 32) X(128, 64) X(768, 32) X(768, 64) X(960, 32) X(960, 64)
+
+bool shape_supported(int D, int R) {
+#define QG_CASE(d, r) if (D == d && R == r) return true;
+  QG_SHAPES(QG_CASE)
+#undef QG_CASE
+  return false;
+}
+
+hipError_t launch_rotate(const float* in, int64_t n, int D, const float* M, float* out, int* zero, int nzero,
+                         hipStream_t st) {
+  if (n <= 0) {
+    if (zero && nzero > 0) hipLaunchKernelGGL(rotate_kernel, dim3(1, 1), dim3(64), 0, st, in, 0, D, M, out, zero, nzero);
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)((n + 15) / 16), (unsigned)(D / 16));
+  hipLaunchKernelGGL(rotate_kernel, grid, dim3(64), 0, st, in, n, D, M, out, zero, nzero);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, const int32_t* G, int R,
+                         uint8_t* blocks, int64_t B, hipStream_t st) {
+  const int wpb = 4;
+  dim3 grid((unsigned)((N + wpb - 1) / wpb));
+  hipLaunchKernelGGL(encode_kernel, grid, dim3(64 * wpb), 0, st, X, ROT, N, D, G, R, blocks, B);
+  return hipGetLastError();
+}
+
+template <int D, int R, bool GV>
+static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t lds, hipStream_t st) {
+  auto kern = search_kernel<D, R, GV>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * wpb), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int D, int R, bool GV>
+static int occupancy_t(int wpb, size_t lds) {
+  int nb = 0;
+  auto kern = search_kernel<D, R, GV>;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 64 * wpb, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_search(int D, int R, bool overflow_pass, const SearchArgs& a, int grid, int wpb, size_t lds,
+                         hipStream_t st) {
+#define QG_CASE(d, r)                                                                            \
+  if (D == d && R == r)                                                                          \
+    return overflow_pass ? launch_search_t<d, r, true>(a, grid, wpb, lds, st)                    \
+                         : launch_search_t<d, r, false>(a, grid, wpb, lds, st);
+  QG_SHAPES(QG_CASE)
+#undef QG_CASE
+  return hipErrorInvalidValue;
+}
+
+int search_occupancy(int D, int R, bool overflow_pass, int wpb, size_t lds) {
+#define QG_CASE(d, r) \
+  if (D == d && R == r) return overflow_pass ? occupancy_t<d, r, true>(wpb, lds) : occupancy_t<d, r, false>(wpb, lds);
+  QG_SHAPES(QG_CASE)
+#undef QG_CASE
+  return 0;
+}
+
+hipError_t launch_estimate(int D, int R, const EstimateArgs& a, int64_t nq, hipStream_t st) {
+  const size_t lds = (size_t)qgl::align16(qgl::lut_rows_padded(D, R) * 32);
+#define QG_CASE(d, r)                                                                           \
+  if (D == d && R == r) {                                                                       \
+    hipLaunchKernelGGL((estimate_kernel<d, r>), dim3((unsigned)nq), dim3(64), lds, st, a);      \
+    return hipGetLastError();                                                                   \
+  }
+  QG_SHAPES(QG_CASE)
+#undef QG_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace qgk

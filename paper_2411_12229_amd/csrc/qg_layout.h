@@ -1,0 +1,53 @@
+// qg_layout.h -- byte layouts shared by the host side of libqg and its kernels.
+//
+// Vertex block (Sec. 3.1.3 of the SymphonyQG paper: raw vector, FastScan data,
+// neighbours, in one contiguous segment), for dimension D and out-degree R:
+//   [0, 4D)                 raw vector, fp32
+//   [4D, 4D + R*D/8)        codes: neighbour j's D-bit RaBitQ code at j*D/8, dim i in byte i/8 bit i%8
+//   next 4R bytes           f_add[R]      fp32
+//   next 4R bytes           f_rescale[R]  fp32
+//   next 4R bytes           nbr[R]        int32 (-1 = empty slot)
+//   zero padding to a multiple of 128 bytes (one HBM-friendly aligned segment).
+#pragma once
+#include <stdint.h>
+
+namespace qgl {
+
+__host__ __device__ constexpr int64_t block_bytes(int D, int R) {
+  return (4LL * D + (int64_t)R * (D / 8) + 12LL * R + 127) / 128 * 128;
+}
+__host__ __device__ constexpr int off_codes(int D) { return 4 * D; }
+__host__ __device__ constexpr int off_fadd(int D, int R) { return 4 * D + R * (D / 8); }
+__host__ __device__ constexpr int off_fres(int D, int R) { return off_fadd(D, R) + 4 * R; }
+__host__ __device__ constexpr int off_nbr(int D, int R) { return off_fadd(D, R) + 8 * R; }
+
+// Per-wavefront LDS of the search kernel (bytes, 16-byte aligned pieces).
+struct SearchLds {
+  int lut, bkey, bid, tkey, tid, ckey, cid, hash, nkey, nid, total;
+};
+
+__host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
+
+// LUT rows are 16 int16 entries (32 bytes).  With two lanes per neighbour the
+// second lane's rows start one padding row later so that the two halves of a
+// wavefront read different LDS banks.
+__host__ __device__ constexpr int lut_rows_padded(int D, int R) { return D / 4 + (64 / R) - 1; }
+
+__host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int hash_cap, int k_cap) {
+  SearchLds s{};
+  int o = 0;
+  s.lut = o;  o += align16(lut_rows_padded(D, R) * 32);
+  s.bkey = o; o += 4 * ef_cap;
+  s.bid = o;  o += 4 * ef_cap;
+  s.tkey = o; o += 4 * 64;
+  s.tid = o;  o += 4 * 64;
+  s.ckey = o; o += 4 * 64;
+  s.cid = o;  o += 4 * 64;
+  s.hash = o; o += 4 * hash_cap;
+  s.nkey = o; o += 4 * k_cap;
+  s.nid = o;  o += 4 * k_cap;
+  s.total = o;
+  return s;
+}
+
+}  // namespace qgl

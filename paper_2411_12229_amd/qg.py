@@ -1,0 +1,240 @@
+"""Thin ctypes binding of libqg (C ABI in include/qg.h).
+
+Argument marshalling only: every step of the search runs in the HIP kernels of
+libqg.so.  torch tensors provide device memory and streams.  The library must
+be built (``python -m paper_2411_12229_amd.build``); importing this module
+without it raises immediately -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqg.so")
+
+QG_OK, QG_EINVAL, QG_ENOMEM, QG_EIO, QG_EFORMAT, QG_EDEVICE, QG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+QG_SEARCH_NO_ME = 1
+QG_SEARCH_SMALL_HASH = 2
+QG_MAX_EF = 2048
+QG_MAX_K = 1024
+
+EXPORTS = ("qg_load_index", "qg_build_index", "qg_save_index", "qg_search", "qg_search_ex", "qg_rotate",
+           "qg_estimate", "qg_copy_blocks", "qg_set_stream", "qg_index_info", "qg_timing", "qg_timing_read",
+           "qg_free_index", "qg_last_error")
+
+
+class QGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libqg error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2411_12229_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "qg_load_index": ([ctypes.c_char_p, c_int, PP], c_int),
+        "qg_build_index": ([P, i64, i32, P, i32, P, i32, c_int, PP], c_int),
+        "qg_save_index": ([P, ctypes.c_char_p], c_int),
+        "qg_search": ([P, P, i64, i32, i32, P, P], c_int),
+        "qg_search_ex": ([P, P, i64, i32, i32, i32, P, P, P], c_int),
+        "qg_rotate": ([P, P, i64, P], c_int),
+        "qg_estimate": ([P, P, P, i64, P, P, P], c_int),
+        "qg_copy_blocks": ([P, i64, i64, P], c_int),
+        "qg_set_stream": ([P, P], c_int),
+        "qg_index_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                           ctypes.POINTER(i64)], c_int),
+        "qg_timing": ([P, c_int], c_int),
+        "qg_timing_read": ([P, c_int, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
+        "qg_free_index": ([P], None),
+        "qg_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def qg_last_error() -> str:
+    return _lib.qg_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != QG_OK:
+        raise QGError(rc, qg_last_error())
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Index:
+    """Owner of a libqg index handle."""
+
+    def __init__(self, handle: ctypes.c_void_p, device: int):
+        self._h = handle
+        self.device = device
+        n, d, r, e, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(_lib.qg_index_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(r), ctypes.byref(e),
+                                  ctypes.byref(b)))
+        self.n, self.d, self.r, self.entry, self.block_bytes = n.value, d.value, r.value, e.value, b.value
+        self._stream = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream) -> None:
+        """Run later work on a torch.cuda.Stream (None = null stream)."""
+        self._stream = stream
+        _check(_lib.qg_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)))
+
+    def search(self, queries: torch.Tensor, k: int, ef: int, flags: int = 0, stats: bool = False):
+        """Algorithm 1 for every row of `queries` -> (ids int32 [nq,k], dists f32 [nq,k][, stats int32 [nq,4]])."""
+        nq = queries.shape[0]
+        dev = queries.device
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=dev) if stats else None
+        qg_search_ex(self, queries, nq, k, ef, flags, ids, dists, st)
+        return (ids, dists, st) if stats else (ids, dists)
+
+    def rotate(self, x: torch.Tensor) -> torch.Tensor:
+        out = torch.empty_like(x)
+        qg_rotate(self, x, x.shape[0], out)
+        return out
+
+    def estimate(self, queries: torch.Tensor, vertices: torch.Tensor):
+        nq = queries.shape[0]
+        S = torch.empty((nq, self.r), dtype=torch.int32, device=queries.device)
+        est = torch.empty((nq, self.r), dtype=torch.float32, device=queries.device)
+        dist = torch.empty((nq,), dtype=torch.float32, device=queries.device)
+        qg_estimate(self, queries, vertices, nq, S, est, dist)
+        return S, est, dist
+
+    def blocks(self, first: int = 0, count: int | None = None) -> torch.Tensor:
+        count = self.n - first if count is None else count
+        out = torch.empty((count, self.block_bytes), dtype=torch.uint8, device=f"cuda:{self.device}")
+        qg_copy_blocks(self, first, count, out)
+        return out
+
+    def save(self, path: str) -> None:
+        qg_save_index(self, path)
+
+    def timing(self, enable: bool) -> None:
+        _check(_lib.qg_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self, kernel: int):
+        n, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.qg_timing_read(self._h, kernel, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def free(self) -> None:
+        if self._h:
+            _lib.qg_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ------------------------------------------- C ABI names, tensor arguments
+
+def qg_load_index(path: str, device: int = 0) -> Index:
+    h = ctypes.c_void_p()
+    _check(_lib.qg_load_index(path.encode(), device, ctypes.byref(h)))
+    return Index(h, device)
+
+
+def qg_build_index(vectors: torch.Tensor, graph: torch.Tensor, rotation: torch.Tensor, entry: int) -> Index:
+    n, d = vectors.shape
+    r = graph.shape[1]
+    if graph.shape[0] != n or tuple(rotation.shape) != (d, d):
+        raise ValueError("shape mismatch between vectors, graph and rotation")
+    h = ctypes.c_void_p()
+    dev = vectors.device.index or 0
+    _check(_lib.qg_build_index(_dev(vectors, torch.float32, "vectors"), n, d, _dev(graph, torch.int32, "graph"), r,
+                               _dev(rotation, torch.float32, "rotation"), int(entry), dev, ctypes.byref(h)))
+    return Index(h, dev)
+
+
+def qg_save_index(idx: Index, path: str) -> None:
+    _check(_lib.qg_save_index(idx.handle, path.encode()))
+
+
+def qg_search_ex(idx: Index, queries, nq: int, k: int, ef: int, flags: int, out_ids, out_dists, out_stats=None):
+    if queries.shape != (nq, idx.d) or out_ids.shape != (nq, k) or out_dists.shape != (nq, k):
+        raise ValueError("shape mismatch")
+    if out_stats is not None and out_stats.shape != (nq, 4):
+        raise ValueError("stats shape mismatch")
+    st = _dev(out_stats, torch.int32, "out_stats") if out_stats is not None else None
+    _check(_lib.qg_search_ex(idx.handle, _dev(queries, torch.float32, "queries"), nq, k, ef, flags,
+                             _dev(out_ids, torch.int32, "out_ids"), _dev(out_dists, torch.float32, "out_dists"), st))
+
+
+def qg_search(idx: Index, queries, nq: int, k: int, ef: int, out_ids, out_dists) -> None:
+    qg_search_ex(idx, queries, nq, k, ef, 0, out_ids, out_dists, None)
+
+
+def qg_rotate(idx: Index, x, n: int, out) -> None:
+    if x.shape != (n, idx.d) or out.shape != (n, idx.d):
+        raise ValueError("shape mismatch")
+    _check(_lib.qg_rotate(idx.handle, _dev(x, torch.float32, "in"), n, _dev(out, torch.float32, "out")))
+
+
+def qg_estimate(idx: Index, queries, vertex_of_query, nq: int, out_S, out_est, out_dist) -> None:
+    if queries.shape != (nq, idx.d) or vertex_of_query.shape != (nq,):
+        raise ValueError("shape mismatch")
+    _check(_lib.qg_estimate(idx.handle, _dev(queries, torch.float32, "queries"),
+                            _dev(vertex_of_query, torch.int32, "vertex_of_query"), nq,
+                            _dev(out_S, torch.int32, "out_S"), _dev(out_est, torch.float32, "out_est"),
+                            _dev(out_dist, torch.float32, "out_dist")))
+
+
+def qg_copy_blocks(idx: Index, first: int, count: int, dst) -> None:
+    if dst.numel() * dst.element_size() < count * idx.block_bytes:
+        raise ValueError("destination too small")
+    _check(_lib.qg_copy_blocks(idx.handle, first, count, _dev(dst, dst.dtype, "dst")))
+
+
+def qg_set_stream(idx: Index, stream) -> None:
+    idx.set_stream(stream)
+
+
+def qg_index_info(idx: Index):
+    return idx.n, idx.d, idx.r, idx.entry, idx.block_bytes
+
+
+def qg_timing(idx: Index, enable: int) -> None:
+    idx.timing(bool(enable))
+
+
+def qg_timing_read(idx: Index, kernel: int):
+    return idx.timing_read(kernel)
+
+
+def qg_free_index(idx: Index) -> None:
+    idx.free()

@@ -1,0 +1,41 @@
+"""The C-ABI library loads and exports every entry point include/qg.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qg.h")
+LIB = os.path.join(ROOT, "paper_2411_12229_amd", "libqg.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_search_boundary():
+    names = declared()
+    for n in ("qg_load_index", "qg_search", "qg_free_index", "qg_last_error", "qg_build_index", "qg_estimate"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        from paper_2411_12229_amd import build
+        build.build()
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_error_paths_without_device():
+    """Argument checks return codes before any device work."""
+    lib = ctypes.CDLL(LIB)
+    lib.qg_last_error.restype = ctypes.c_char_p
+    out = ctypes.c_void_p(1)
+    assert lib.qg_load_index(None, 0, ctypes.byref(out)) == -1 and out.value is None
+    assert lib.qg_load_index(b"/nonexistent/x.qgi", 0, ctypes.byref(out)) == -3
+    assert b"cannot open" in lib.qg_last_error()
+    assert lib.qg_search(None, None, 0, 10, 10, None, None) == -1
+    lib.qg_free_index(None)

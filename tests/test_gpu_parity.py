@@ -1,0 +1,243 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: rotated queries, codes, factors, FastScan sums and estimates bit-exact;
+result ids identical and distances bit-equal (the requirement is 1e-5
+relative; the canonical arithmetic makes them equal); per-query counters equal.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2411_12229_amd import qg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    X, Q = synth.gen_data(1)
+    M = synth.rotation(128, synth.seed(1, "rotation"))
+    G = synth.knn_graph(X, 32, synth.seed(1, "long"))
+    e = synth.medoid(X)
+    blocks = oracle.encode(X, G, M)
+    say("cfg1 index: N=10000 D=128 R=32")
+    idx = qg.qg_build_index(T(X), T(G), T(M), e)
+    return dict(X=X, Q=Q, M=M, G=G, e=e, blocks=blocks, idx=idx)
+
+
+def _search(idx, Q, k, ef, flags=0):
+    ids, dists, st = idx.search(T(Q), k, ef, flags=flags, stats=True)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
+
+
+def _assert_same(gpu, orc, ctx):
+    gi, gd, gs = gpu
+    oi, od, os_ = orc
+    bad = np.nonzero((gi != oi).any(axis=1))[0]
+    assert bad.size == 0, f"{ctx}: ids differ for queries {bad[:10].tolist()}"
+    assert np.array_equal(gd, od), f"{ctx}: distances differ"
+    assert np.array_equal(gs[:, :3], os_[:, :3]), f"{ctx}: counters differ"
+
+
+def test_rotation_bit_exact(cfg1):
+    """Rotated queries (Eq. rotation) equal the oracle's fp64 chain bit for bit."""
+    idx = cfg1["idx"]
+    say("rotate cfg1 queries")
+    out = idx.rotate(T(cfg1["Q"])).cpu().numpy()
+    assert np.array_equal(out, oracle.rotate(cfg1["M"], cfg1["Q"]))
+    Xi, Qi = synth.gen_data(2, n=300, nq=77, ncent=5)
+    M2 = synth.rotation(128, 99)
+    G2 = synth.knn_graph(Xi, 32, 3)
+    idx2 = qg.qg_build_index(T(Xi), T(G2), T(M2), 0)
+    out2 = idx2.rotate(T(Qi)).cpu().numpy()
+    assert np.array_equal(out2, oracle.rotate(M2, Qi))
+
+
+def test_encode_bit_exact_cfg1(cfg1):
+    """Every block (raw vector, codes, factors, ids, padding) equals the oracle's bytes."""
+    say("encode cfg1")
+    got = cfg1["idx"].blocks().cpu().numpy()
+    exp = cfg1["blocks"]
+    bad = np.nonzero((got != exp).any(axis=1))[0]
+    assert bad.size == 0, f"blocks differ at vertices {bad[:10].tolist()}"
+
+
+@pytest.mark.parametrize("D,R,cfg", [(96, 32, 5), (960, 64, 3), (768, 32, 4), (128, 64, 1)])
+def test_encode_bit_exact_shapes(D, R, cfg):
+    X, Q = synth.gen_data(cfg, n=600, nq=20, D=D) if cfg != 4 else synth.gen_data(cfg, n=600, nq=20)
+    M = synth.rotation(D, 7)
+    G = synth.knn_graph(X, R, 8, n_long=8)
+    G[5, 3] = -1  # an empty slot
+    say(f"encode D={D} R={R}")
+    idx = qg.qg_build_index(T(X), T(G), T(M), synth.medoid(X))
+    got = idx.blocks().cpu().numpy()
+    assert np.array_equal(got, oracle.encode(X, G, M))
+
+
+def test_estimate_bit_exact(cfg1):
+    """FastScan sums S_j are bit-exact integers and the estimates equal the oracle's."""
+    rng = np.random.default_rng(3)
+    vs = rng.integers(0, 10000, 64).astype(np.int32)
+    Q = cfg1["Q"][:64]
+    say("estimate cfg1")
+    S, est, dist = cfg1["idx"].estimate(T(Q), T(vs))
+    S, est, dist = S.cpu().numpy(), est.cpu().numpy(), dist.cpu().numpy()
+    qrot = oracle.rotate(cfg1["M"], Q)
+    for i in range(64):
+        oS, oe, od = oracle.estimate(cfg1["blocks"], 128, 32, Q[i], qrot[i], int(vs[i]))
+        assert np.array_equal(S[i], oS)
+        assert np.array_equal(est[i], oe)
+        assert dist[i] == od
+
+
+def test_search_parity_cfg1(cfg1):
+    """200 queries, k = 10, ef = 64: identical ids, distances and counters."""
+    c = cfg1
+    say("search cfg1 k=10 ef=64")
+    gpu = _search(c["idx"], c["Q"], 10, 64)
+    orc = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], 10, 64, with_stats=True)
+    _assert_same(gpu, orc, "cfg1")
+    gt, _ = synth.ground_truth(c["X"], c["Q"], 10)
+    say(f"recall@10 = {synth.recall(gpu[0], gt, 10):.4f}")
+
+
+@pytest.mark.parametrize("k,ef,nq", [(10, 16, 200), (1, 1, 3), (100, 100, 257), (10, 512, 64), (150, 7, 5),
+                                     (64, 64, 1), (10, 2048, 8)])
+def test_search_parity_sweep(cfg1, k, ef, nq):
+    c = cfg1
+    Q = np.concatenate([c["Q"], c["Q"] + 0.05])[:nq]
+    say(f"search cfg1 k={k} ef={ef} nq={nq}")
+    gpu = _search(c["idx"], Q, k, ef)
+    orc = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], Q, k, ef, with_stats=True)
+    _assert_same(gpu, orc, f"k={k} ef={ef}")
+
+
+def test_search_overflow_path(cfg1):
+    """With a 128-slot on-chip visited set most queries move to the global
+    bitset path; results must not change."""
+    c = cfg1
+    say("search cfg1 overflow path")
+    gpu = _search(c["idx"], c["Q"], 10, 64, flags=qg.QG_SEARCH_SMALL_HASH)
+    assert gpu[2][:, 3].sum() > 0, "overflow path not taken"
+    orc = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], 10, 64, with_stats=True)
+    _assert_same(gpu, orc, "overflow")
+
+
+@pytest.mark.parametrize("D,R,cfg", [(96, 32, 5), (960, 64, 3), (768, 32, 4), (128, 64, 1)])
+def test_search_parity_shapes(D, R, cfg):
+    X, Q = synth.gen_data(cfg, n=3000, nq=40, D=D) if cfg != 4 else synth.gen_data(cfg, n=3000, nq=40)
+    M = synth.rotation(D, 17)
+    G = synth.knn_graph(X, R, 18, n_long=8)
+    e = synth.medoid(X)
+    say(f"search D={D} R={R}")
+    idx = qg.qg_build_index(T(X), T(G), T(M), e)
+    blocks = oracle.encode(X, G, M)
+    for k, ef in ((10, 32), (100, 128)):
+        gpu = _search(idx, Q, k, ef)
+        orc = oracle.search(blocks, D, R, e, M, Q, k, ef, with_stats=True)
+        _assert_same(gpu, orc, f"D={D} R={R} k={k} ef={ef}")
+
+
+def test_search_parity_algorithm2_graph():
+    """Same bar on a graph built by the oracle's Algorithm 2 (exact degree R)."""
+    X, Q = synth.gen_data(1, n=2000, nq=50)
+    M = synth.rotation(128, 5)
+    e = synth.medoid(X)
+    G = oracle.build_graph(X, 32, 64, 2, M, e, synth.random_graph(2000, 32, 6), synth.random_graph(2000, 32, 7))
+    say("search on an Algorithm 2 graph")
+    idx = qg.qg_build_index(T(X), T(G), T(M), e)
+    blocks = oracle.encode(X, G, M)
+    gpu = _search(idx, Q, 10, 48)
+    orc = oracle.search(blocks, 128, 32, e, M, Q, 10, 48, with_stats=True)
+    _assert_same(gpu, orc, "alg2 graph")
+
+
+def test_file_roundtrip(cfg1, tmp_path):
+    """An oracle-written file loads and searches identically; the library's own
+    file is byte-identical to the oracle's."""
+    c = cfg1
+    p1 = str(tmp_path / "oracle.qgi")
+    oracle.write_index(p1, c["blocks"], 128, 32, c["e"], c["M"])
+    say("load oracle-written index")
+    idx = qg.qg_load_index(p1)
+    gpu = _search(idx, c["Q"][:50], 10, 32)
+    orc = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"][:50], 10, 32, with_stats=True)
+    _assert_same(gpu, orc, "loaded")
+    p2 = str(tmp_path / "lib.qgi")
+    c["idx"].save(p2)
+    assert open(p1, "rb").read() == open(p2, "rb").read()
+    idx.free()
+
+
+def test_bad_inputs(cfg1, tmp_path):
+    c = cfg1
+    idx = c["idx"]
+    Qd = T(c["Q"][:4])
+    ids = torch.empty((4, 10), dtype=torch.int32, device=DEV)
+    d = torch.empty((4, 10), dtype=torch.float32, device=DEV)
+    for k, ef, code in ((0, 10, qg.QG_EINVAL), (10, 0, qg.QG_EINVAL), (10, 4096, qg.QG_EUNSUPPORTED),
+                        (2000, 10, qg.QG_EUNSUPPORTED)):
+        with pytest.raises(qg.QGError) as ex:
+            qg._check(qg.lib().qg_search(idx.handle, qg._dev(Qd, torch.float32, "q"), 4, k, ef,
+                                         qg._dev(ids, torch.int32, "i"), qg._dev(d, torch.float32, "d")))
+        assert ex.value.code == code
+    assert qg.lib().qg_search(idx.handle, None, 0, 10, 10, None, None) == qg.QG_OK  # nq = 0: no-op
+    assert qg.lib().qg_search(idx.handle, None, 4, 10, 10, None, None) == qg.QG_EINVAL
+    G = c["G"].copy()
+    G[7, 2] = 10000  # out of range
+    with pytest.raises(qg.QGError) as ex:
+        qg.qg_build_index(T(c["X"]), T(G), T(c["M"]), c["e"])
+    assert ex.value.code == qg.QG_EINVAL
+    p = str(tmp_path / "x.qgi")
+    oracle.write_index(p, c["blocks"][:100].copy(), 128, 32, 0, c["M"])
+    raw = bytearray(open(p, "rb").read())
+    raw[-5] ^= 0xFF
+    open(p, "wb").write(bytes(raw))
+    with pytest.raises(qg.QGError) as ex:
+        qg.qg_load_index(p)
+    assert ex.value.code == qg.QG_EFORMAT
+    open(p, "wb").write(bytes(raw[:5000]))
+    with pytest.raises(qg.QGError) as ex:
+        qg.qg_load_index(p)
+    assert ex.value.code == qg.QG_EFORMAT
+    with pytest.raises(qg.QGError) as ex:
+        qg.qg_load_index(str(tmp_path / "missing.qgi"))
+    assert ex.value.code == qg.QG_EIO
+
+
+def test_deterministic_batch_independent_and_stream(cfg1):
+    c = cfg1
+    say("determinism")
+    a = _search(c["idx"], c["Q"], 10, 48)
+    b = _search(c["idx"], c["Q"], 10, 48)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    for i in (0, 77, 199):
+        s = _search(c["idx"], c["Q"][i:i + 1], 10, 48)
+        assert np.array_equal(s[0][0], a[0][i]) and np.array_equal(s[1][0], a[1][i])
+    st = torch.cuda.Stream()
+    c["idx"].set_stream(st)
+    with torch.cuda.stream(st):
+        Qd = T(c["Q"])
+        ids, dists = c["idx"].search(Qd, 10, 48)
+    st.synchronize()
+    c["idx"].set_stream(None)
+    assert np.array_equal(ids.cpu().numpy(), a[0])
