@@ -14,6 +14,8 @@ queries, metric).  All draws use numpy ``Generator(PCG64(seed))`` with seeds
 from __future__ import annotations
 
 import math
+import sys
+import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -195,7 +197,10 @@ def _topk_rows_torch(X, Y, k: int, exclude_self: bool, device):
     ids_out = np.empty((Y.shape[0], k), np.int64)
     d_out = np.empty((Y.shape[0], k), np.float64)
     chunk = max(256, min(8192, int(2e9 // max(N, 1))))
+    t0 = time.time()
     for s in range(0, Y.shape[0], chunk):
+        if s and (s // chunk) % 100 == 0:
+            print(f"[synth] brute force {s}/{Y.shape[0]} rows, {time.time() - t0:.0f}s", file=sys.stderr, flush=True)
         y = torch.from_numpy(np.ascontiguousarray(Y[s:s + chunk])).to(device)
         d = xx[None, :] - 2.0 * (y @ Xt.T)
         if exclude_self:
