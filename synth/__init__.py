@@ -122,7 +122,7 @@ def rotation(D: int, s: int) -> np.ndarray:
     Qm, Rm = np.linalg.qr(G)
     P = Qm * np.sign(np.diag(Rm))[None, :]
     M = np.round(P.T * 2.0 ** 24) / 2.0 ** 24
-    return M.astype(np.float32)
+    return np.ascontiguousarray(M, dtype=np.float32)
 
 
 def random_graph(N: int, R: int, s: int) -> np.ndarray:
