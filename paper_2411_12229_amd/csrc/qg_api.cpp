@@ -390,11 +390,13 @@ int qg_search_ex(const qg_index* cidx, const float* queries, int64_t nq, int32_t
   int rc = ensure_scratch(idx, nq);
   if (rc) return rc;
 
-  const int ef_cap = (ef + 63) / 64 * 64;
-  const int k_cap = (k + 63) / 64 * 64;
-  // visited hash: room for about 8 ef ids at load <= 1/2, at least 128 slots
-  int hbits = 7;
-  while ((1 << hbits) < 8 * ef && hbits < 14 && !(flags & QG_SEARCH_SMALL_HASH)) ++hbits;
+  const int ef_cap = (ef + 3) / 4 * 4;
+  const int k_cap = (k + 3) / 4 * 4;
+  // visited hash: 2^h >= 3 ef slots (at least 256), filled to at most one half;
+  // queries that visit more finish in the overflow pass
+  int hbits = 8;
+  while ((1 << hbits) < 3 * ef && hbits < 14) ++hbits;
+  if (flags & QG_SEARCH_SMALL_HASH) hbits = 7;
   qgk::SearchArgs a{};
   a.blocks = idx->blocks;
   a.block_bytes = idx->block_bytes;

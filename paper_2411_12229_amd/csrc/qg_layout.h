@@ -21,7 +21,8 @@ __host__ __device__ constexpr int off_fadd(int D, int R) { return 4 * D + R * (D
 __host__ __device__ constexpr int off_fres(int D, int R) { return off_fadd(D, R) + 4 * R; }
 __host__ __device__ constexpr int off_nbr(int D, int R) { return off_fadd(D, R) + 8 * R; }
 
-// Per-wavefront LDS of the search kernel (bytes, 16-byte aligned pieces).
+// Per-wavefront LDS of the search kernel (bytes).  ef_cap and k_cap are
+// multiples of 4 so every piece stays 16-byte aligned.
 struct SearchLds {
   int lut, bkey, bid, tkey, tid, ckey, cid, hash, nkey, nid, total;
 };
@@ -39,10 +40,10 @@ __host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int ha
   s.lut = o;  o += align16(lut_rows_padded(D, R) * 32);
   s.bkey = o; o += 4 * ef_cap;
   s.bid = o;  o += 4 * ef_cap;
-  s.tkey = o; o += 4 * 64;
-  s.tid = o;  o += 4 * 64;
-  s.ckey = o; o += 4 * 64;
-  s.cid = o;  o += 4 * 64;
+  s.tkey = o; o += 4 * R;
+  s.tid = o;  o += 4 * R;
+  s.ckey = o; o += 4 * R;
+  s.cid = o;  o += 4 * R;
   s.hash = o; o += 4 * hash_cap;
   s.nkey = o; o += 4 * k_cap;
   s.nid = o;  o += 4 * k_cap;

@@ -71,22 +71,26 @@ def gen_data(cfg: int, n: int | None = None, nq: int | None = None, D: int | Non
         Q = mu[gq.integers(0, 16, nq)] + 0.3 * gq.standard_normal((nq, D))
         return X.astype(np.float32), Q.astype(np.float32)
     if cfg == 2:
-        # 1000 Gaussian components; each has a rank-12 covariance plus a small
-        # isotropic floor, so the data has a low local dimension as SIFT does
-        # (isotropic 128-d components would make all neighbours equidistant).
+        # A 1000-component Gaussian mixture with SIFT's low local dimension:
+        # components are overlapping blobs in a shared 12-d latent space
+        # (centre z_c ~ N(0, I), within-component N(0, 0.6^2 I), mapped to 128-d
+        # by one random W), plus 4 component-specific directions and an
+        # isotropic floor.  Values are clipped to [0, 255] and rounded.
         ncent = kw.get("ncent", 1000)
-        r = 12
-        mu = (64.0 + 32.0 * g.standard_normal((ncent, D))).astype(np.float32)
-        A = (g.standard_normal((ncent, D, r)) * math.sqrt((576.0 - 16.0) / r)).astype(np.float32)
+        dl, dc = 12, 4
+        W = (g.standard_normal((D, dl)) * (26.0 / math.sqrt(dl))).astype(np.float32)
+        zc = g.standard_normal((ncent, dl)).astype(np.float32)
+        Ac = (g.standard_normal((ncent, D, dc)) * (8.0 / math.sqrt(dc))).astype(np.float32)
 
         def draw(gg, m):
             out = np.empty((m, D), np.float32)
             lab = gg.integers(0, ncent, m)
             for s in range(0, m, 1 << 16):
                 e = min(m, s + (1 << 16))
-                z = gg.standard_normal((e - s, r), dtype=np.float32)
-                v = mu[lab[s:e]] + np.einsum("bdr,br->bd", A[lab[s:e]], z)
-                v += np.float32(4.0) * gg.standard_normal((e - s, D), dtype=np.float32)
+                zz = zc[lab[s:e]] + np.float32(0.6) * gg.standard_normal((e - s, dl), dtype=np.float32)
+                v = 64.0 + zz @ W.T
+                v += np.einsum("bdr,br->bd", Ac[lab[s:e]], gg.standard_normal((e - s, dc), dtype=np.float32))
+                v += np.float32(3.0) * gg.standard_normal((e - s, D), dtype=np.float32)
                 out[s:e] = np.rint(np.clip(v, 0.0, 255.0))
             return out
 
