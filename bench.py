@@ -43,6 +43,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=10_000, help="queries searched by the CPU oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--save-index", default="")
+    ap.add_argument("--ef", type=int, default=0, help="skip the sweep and time this beam size")
+    ap.add_argument("--load-index", default="", help="search a saved index (no recall: ground truth is not rebuilt)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the query path shards by "
@@ -57,22 +61,38 @@ def main():
     dev = torch.device("cuda:0")
     cfg = synth.CONFIGS[2]
     D, R, k = cfg.D, cfg.R, cfg.k
-    t0 = time.time()
-    X, Q = synth.gen_data(2, n=args.n, nq=args.nq)
-    M = synth.rotation(D, synth.seed(2, "rotation"))
-    log(f"[bench] data {X.shape} queries {Q.shape} in {time.time() - t0:.1f}s")
-    t0 = time.time()
-    G = synth.knn_graph(X, R, synth.seed(2, "long"), device=dev)
-    entry = synth.medoid(X)
-    log(f"[bench] input graph (k-NN + random links) in {time.time() - t0:.1f}s; entry {entry}")
-    Xd, Gd, Md, Qd = (torch.from_numpy(a).to(dev) for a in (X, G, M, Q))
-    t0 = time.time()
-    idx = qg.qg_build_index(Xd, Gd, Md, entry)
-    log(f"[bench] GPU encode {idx.n} blocks x {idx.block_bytes} B in {time.time() - t0:.2f}s")
-    del Xd, Gd
-    if args.save_index:
-        idx.save(args.save_index)
-    gt, gt_d = synth.ground_truth(X, Q, k, device=dev)
+    if args.load_index:
+        if not args.ef:
+            sys.exit("--load-index needs --ef")
+        _, Q = synth.gen_data(2, n=1, nq=args.nq)  # queries do not depend on n
+        idx = qg.qg_load_index(args.load_index)
+        X = G = M = entry = gt = None
+        Qd = torch.from_numpy(Q).to(dev)
+        log(f"[bench] loaded {args.load_index}: {idx.n} blocks")
+    else:
+        t0 = time.time()
+        X, Q = synth.gen_data(2, n=args.n, nq=args.nq)
+        M = synth.rotation(D, synth.seed(2, "rotation"))
+        log(f"[bench] data {X.shape} queries {Q.shape} in {time.time() - t0:.1f}s")
+        t0 = time.time()
+        G = synth.knn_graph(X, R, synth.seed(2, "long"), device=dev)
+        entry = synth.medoid(X)
+        log(f"[bench] input graph (k-NN + random links) in {time.time() - t0:.1f}s; entry {entry}")
+        Xd, Gd, Md, Qd = (torch.from_numpy(a).to(dev) for a in (X, G, M, Q))
+        t0 = time.time()
+        idx = qg.qg_build_index(Xd, Gd, Md, entry)
+        log(f"[bench] GPU encode {idx.n} blocks x {idx.block_bytes} B in {time.time() - t0:.2f}s")
+        del Xd, Gd
+        if args.save_index:
+            idx.save(args.save_index)
+        gt, gt_d = synth.ground_truth(X, Q, k, device=dev)
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 3 x 1 GiB device copies")
 
     stream = torch.cuda.Stream()
     idx.set_stream(stream)
@@ -88,9 +108,9 @@ def main():
 
     sweep = []
     chosen = None
-    for ef in EFS:
+    for ef in ((args.ef,) if args.ef else EFS):
         ids, dists, st = run(ef, stats=True)
-        rec = synth.recall(ids.cpu().numpy(), gt, k)
+        rec = synth.recall(ids.cpu().numpy(), gt, k) if gt is not None else float("nan")
         s = st.cpu().numpy()
         t1 = time.time()
         for _ in range(3):
@@ -101,7 +121,7 @@ def main():
                       "overflow_queries": int(s[:, 3].sum())})
         log(f"[bench] ef={ef:4d} recall@10={rec:.4f} E_q mean {s[:, 0].mean():.1f} max {s[:, 0].max()} "
             f"~{qps:,.0f} q/s")
-        if chosen is None and rec >= args.target:
+        if chosen is None and (rec >= args.target or args.ef):
             chosen = (ef, rec, s)
             if len(sweep) >= 2 and ef >= 64:
                 break
@@ -142,7 +162,7 @@ def main():
                 "rotate_kernel_ms": round(rot_ms / max(n_rot, 1), 4)}
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and X is not None:
         sys.path.insert(0, os.path.join(ROOT, "oracle"))
         import oracle
         t0 = time.time()
