@@ -43,6 +43,28 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// x from lane (lane ^ s).  s = 1, 2: DPP quad permutes; 4, 8, 16: LDS swizzle
+// in bit mode (xor within 32 lanes); 32: bpermute.  Pure data movement, so a
+// butterfly built on it adds exactly p[l] + p[l^s].
+template <int S>
+__device__ __forceinline__ float xor_lane(float x) {
+  const int v = __float_as_int(x);
+  if constexpr (S == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
+  if constexpr (S == 2) return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
+  if constexpr (S == 4 || S == 8 || S == 16) return __int_as_float(__builtin_amdgcn_ds_swizzle(v, (S << 10) | 0x1F));
+  return __shfl_xor(x, 32, 64);
+}
+
+__device__ __forceinline__ float butterfly_f(float p) {
+  p = p + xor_lane<32>(p);
+  p = p + xor_lane<16>(p);
+  p = p + xor_lane<8>(p);
+  p = p + xor_lane<4>(p);
+  p = p + xor_lane<2>(p);
+  p = p + xor_lane<1>(p);
+  return p;
+}
+
 // Exact squared distance |q - x|^2 (implicit re-ranking, Sec. 3.1.2): dim i
 // into lane i mod 64 by a fused multiply-add chain in ascending i, then the
 // xor butterfly p[l] + p[l^s], s = 32 ... 1.  Every lane ends with the result.
@@ -54,9 +76,7 @@ __device__ __forceinline__ float exact_dist(const float (&qv)[DPL], const float 
     float d = qv[t] - xv[t];
     p = __builtin_fmaf(d, d, p);
   }
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) p = p + __shfl_xor(p, s, 64);
-  return p;
+  return butterfly_f(p);
 }
 
 // ---------------------------------------------------------------- rotation
@@ -288,12 +308,12 @@ __device__ __forceinline__ bool visited_contains(const Visited& v, uint32_t id) 
     return (w >> (id & 31)) & 1u;
   } else {
     uint32_t s = v.slot0(id);
-    for (;;) {
-      uint32_t e = v.tab[s];
-      if (e == id) return true;
-      if (e == kEmpty) return false;
+    uint32_t e = v.tab[s];
+    while (e != id && e != kEmpty) {  // most probes end at the first slot
       s = (s + 1) & v.mask;
+      e = v.tab[s];
     }
+    return e == id;
   }
 }
 
@@ -331,12 +351,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   const int lane = lane_id();
   const int ef = a.ef, k = a.k;
   int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
-  float* bkey = reinterpret_cast<float*>(lds + L.bkey);
-  uint32_t* bid = reinterpret_cast<uint32_t*>(lds + L.bid);
-  float* tkey = reinterpret_cast<float*>(lds + L.tkey);
-  uint32_t* tid = reinterpret_cast<uint32_t*>(lds + L.tid);
-  float* ckey = reinterpret_cast<float*>(lds + L.ckey);
-  uint32_t* cid = reinterpret_cast<uint32_t*>(lds + L.cid);
+  uint2* beam = reinterpret_cast<uint2*>(lds + L.beam);    // sorted (key bits, id | checked)
+  uint2* ctmp = reinterpret_cast<uint2*>(lds + L.ctmp);    // candidates in lane order
+  uint2* csort = reinterpret_cast<uint2*>(lds + L.csort);  // candidates in (key, id) order
+  int* lbarr = reinterpret_cast<int*>(lds + L.lb);
   float* nkey = reinterpret_cast<float*>(lds + L.nkey);
   uint32_t* nid = reinterpret_cast<uint32_t*>(lds + L.nid);
 
@@ -369,13 +387,12 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     BV e;
     e.load(a.blocks + (int64_t)a.entry * a.block_bytes, lane);
     const float de = exact_dist<DPL>(qv, e.x);
-    if (lane == 0) {
-      bkey[0] = de;
-      bid[0] = (uint32_t)a.entry;
-    }
+    if (lane == 0) beam[0] = make_uint2(__float_as_uint(de), (uint32_t)a.entry);
     wave_sync();
   }
   int size = 1, cursor = 0, nnc = 0;
+  float nn_wk = 0.0f;  // worst (distance, id) in NN once it holds k entries
+  uint32_t nn_wi = 0;
   int expansions = 0, pops = 0, appended = 0;
 
   for (;;) {
@@ -383,7 +400,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     int c = -1;
     while (cursor < size) {
       const int i = cursor + lane;
-      const bool un = (i < size) && !(bid[i < size ? i : 0] & kChecked);
+      const bool un = (i < size) && !(beam[i < size ? i : 0].y & kChecked);
       const uint64_t m = ballot(un);
       if (m) {
         c = cursor + first_lane(m);
@@ -392,9 +409,9 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       cursor += 64;
     }
     if (c < 0) break;
-    const uint32_t p = bid[c];
+    const uint32_t p = beam[c].y;
     wave_sync();
-    if (lane == 0) bid[c] = p | kChecked;
+    if (lane == 0) beam[c].y = p | kChecked;
     wave_sync();
     cursor = c + 1;
     ++pops;
@@ -413,7 +430,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const float dp = exact_dist<DPL>(qv, b.x);
 
     // implicit re-ranking: NN keeps the k smallest (distance, id) seen
-    if (nnc < k || kv_less(dp, p, nkey[nnc - 1], nid[nnc - 1])) {
+    if (nnc < k || kv_less(dp, p, nn_wk, nn_wi)) {
       int pos = 0;
       for (int base = 0; base < nnc; base += 64) {
         const int i = base + lane;
@@ -444,6 +461,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       }
       wave_sync();
       nnc = nnc < k ? nnc + 1 : k;
+      if (nnc == k) {
+        nn_wk = nkey[k - 1];
+        nn_wi = nid[k - 1];
+      }
     }
 
     // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
@@ -453,67 +474,62 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     bool valid = (lane % LPN == 0) && b.nb >= 0;
     if (valid) valid = !visited_contains<GV>(vis, nb);
     appended += __popcll(ballot(valid));
-    if (size == ef && valid) valid = kv_less(est, nb, bkey[ef - 1], bid[ef - 1] & kIdMask);
+    if (size == ef && valid) {
+      const uint2 tail = beam[ef - 1];
+      valid = kv_less(est, nb, __uint_as_float(tail.x), tail.y & kIdMask);
+    }
     const uint64_t V = ballot(valid);
     const int nv = __popcll(V);
     if (nv == 0) continue;
 
-    // order the candidates by (estimate, id)
-    const int r = lanes_below(V);
-    if (valid) {
-      tkey[r] = est;
-      tid[r] = nb;
-    }
+    // rank the candidates by (estimate, id)
+    if (valid) ctmp[lanes_below(V)] = make_uint2(__float_as_uint(est), nb);
     wave_sync();
     int sidx = 0;
-    if (valid)
-      for (int t = 0; t < nv; ++t) sidx += kv_less(tkey[t], tid[t], est, nb);
-    int lb = 0;  // old entries placed before this candidate: those <= it
     if (valid) {
-      int lo = 0, hi = size;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (!kv_less(est, nb, bkey[mid], bid[mid] & kIdMask))
-          lo = mid + 1;
-        else
-          hi = mid;
+      for (int t = 0; t < nv; ++t) {
+        const uint2 o = ctmp[t];
+        sidx += kv_less(__uint_as_float(o.x), o.y, est, nb);
       }
-      lb = lo;
-      ckey[sidx] = est;
-      cid[sidx] = nb;
+      csort[sidx] = make_uint2(__float_as_uint(est), nb);
     }
     wave_sync();
-    // move old entries up by the number of candidates strictly before them,
-    // top chunk first so nothing is overwritten before it is read
+    // Old entry i moves up by cnt_i = #candidates strictly before it; the
+    // candidate of rank r lands after lb_r = #old entries <= it, and since
+    // cnt is non-decreasing, lb_r = i + 1 for cnt_i <= r < cnt_{i+1}.  Chunks
+    // go top down so no entry is overwritten before it is read.
+    int above = nv;  // cnt of the entry just above the current chunk (nv past the end)
     for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {
       const int i = base + lane;
-      float kk = 0.0f;
-      uint32_t ii = 0;
-      int np = ef;
+      uint2 e = make_uint2(0u, 0u);
+      int cnt = nv;
       if (i < size) {
-        kk = bkey[i];
-        ii = bid[i];
-        int lo = 0, hi = nv;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (kv_less(ckey[mid], cid[mid], kk, ii & kIdMask))
-            lo = mid + 1;
-          else
-            hi = mid;
+        e = beam[i];
+        const float ek = __uint_as_float(e.x);
+        const uint32_t ei = e.y & kIdMask;
+        cnt = 0;
+        for (int t = 0; t < nv; ++t) {
+          const uint2 o = csort[t];
+          cnt += kv_less(__uint_as_float(o.x), o.y, ek, ei);
         }
-        np = i + lo;
       }
+      int up = __shfl_down(cnt, 1, 64);
+      if (lane == 63) up = above;
+      if (i < size) {
+        const int hi = (i + 1 < size) ? up : nv;
+        for (int r = cnt; r < hi; ++r) lbarr[r] = i + 1;
+        if (i == 0)
+          for (int r = 0; r < cnt; ++r) lbarr[r] = 0;
+      }
+      above = __shfl(cnt, 0, 64);
       wave_sync();
-      if (np < ef) {
-        bkey[np] = kk;
-        bid[np] = ii;
-      }
+      if (i < size && i + cnt < ef) beam[i + cnt] = e;
       wave_sync();
     }
-    const int npos = sidx + lb;
-    if (valid && npos < ef) {
-      bkey[npos] = est;
-      bid[npos] = nb;
+    int npos = ef;
+    if (valid) {
+      npos = sidx + lbarr[sidx];
+      if (npos < ef) beam[npos] = make_uint2(__float_as_uint(est), nb);
     }
     wave_sync();
     const int first = __shfl(npos, first_lane(ballot(valid && sidx == 0)), 64);
