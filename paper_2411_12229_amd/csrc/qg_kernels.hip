@@ -33,6 +33,13 @@ __device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((unsigned
 
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// Values every lane of the wavefront holds identically (broadcast LDS reads,
+// ballot-derived counts, butterfly results) are moved to scalar registers so
+// control flow on them is a scalar branch.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+
 // (key, id) lexicographic order.
 __device__ __forceinline__ bool kv_less(float ka, uint32_t ia, float kb, uint32_t ib) {
   return ka < kb || (ka == kb && ia < ib);
@@ -386,8 +393,8 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   {
     BV e;
     e.load(a.blocks + (int64_t)a.entry * a.block_bytes, lane);
-    const float de = exact_dist<DPL>(qv, e.x);
-    if (lane == 0) beam[0] = make_uint2(__float_as_uint(de), (uint32_t)a.entry);
+    const float de = uni(exact_dist<DPL>(qv, e.x));
+    beam[0] = make_uint2(__float_as_uint(de), (uint32_t)a.entry);
     wave_sync();
   }
   int size = 1, cursor = 0, nnc = 0;
@@ -403,15 +410,15 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       const bool un = (i < size) && !(beam[i < size ? i : 0].y & kChecked);
       const uint64_t m = ballot(un);
       if (m) {
-        c = cursor + first_lane(m);
+        c = uni(cursor + first_lane(m));
         break;
       }
       cursor += 64;
     }
     if (c < 0) break;
-    const uint32_t p = beam[c].y;
+    const uint32_t p = uni(beam[c].y);
     wave_sync();
-    if (lane == 0) beam[c].y = p | kChecked;
+    beam[c].y = p | kChecked;  // every lane stores the same word
     wave_sync();
     cursor = c + 1;
     ++pops;
@@ -427,7 +434,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 
     BV b;
     b.load(a.blocks + (int64_t)p * a.block_bytes, lane);
-    const float dp = exact_dist<DPL>(qv, b.x);
+    const float dp = uni(exact_dist<DPL>(qv, b.x));
 
     // implicit re-ranking: NN keeps the k smallest (distance, id) seen
     if (nnc < k || kv_less(dp, p, nn_wk, nn_wi)) {
@@ -455,15 +462,14 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         wave_sync();
         if (base < pos) break;
       }
-      if (lane == 0) {
-        nkey[pos] = dp;
-        nid[pos] = p;
-      }
+      pos = uni(pos);
+      nkey[pos] = dp;  // same value from every lane
+      nid[pos] = p;
       wave_sync();
       nnc = nnc < k ? nnc + 1 : k;
       if (nnc == k) {
-        nn_wk = nkey[k - 1];
-        nn_wi = nid[k - 1];
+        nn_wk = uni(nkey[k - 1]);
+        nn_wi = uni(nid[k - 1]);
       }
     }
 
@@ -479,7 +485,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       valid = kv_less(est, nb, __uint_as_float(tail.x), tail.y & kIdMask);
     }
     const uint64_t V = ballot(valid);
-    const int nv = __popcll(V);
+    const int nv = uni((int)__popcll(V));
     if (nv == 0) continue;
 
     // rank the candidates by (estimate, id)
@@ -521,7 +527,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         if (i == 0)
           for (int r = 0; r < cnt; ++r) lbarr[r] = 0;
       }
-      above = __shfl(cnt, 0, 64);
+      above = uni(cnt);
       wave_sync();
       if (i < size && i + cnt < ef) beam[i + cnt] = e;
       wave_sync();
@@ -532,7 +538,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       if (npos < ef) beam[npos] = make_uint2(__float_as_uint(est), nb);
     }
     wave_sync();
-    const int first = __shfl(npos, first_lane(ballot(valid && sidx == 0)), 64);
+    const int first = uni(__shfl(npos, first_lane(ballot(valid && sidx == 0)), 64));
     if (first < cursor) cursor = first;
     size = (size + nv < ef) ? size + nv : ef;
   }
