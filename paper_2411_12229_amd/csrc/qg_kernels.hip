@@ -401,6 +401,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   float nn_wk = 0.0f;  // worst (distance, id) in NN once it holds k entries
   uint32_t nn_wi = 0;
   int expansions = 0, pops = 0, appended = 0;
+  // Next-vertex prefetch (Sec. 3.1.4): once the new candidates are ranked,
+  // the next pop is known, and its block is loaded while the beam is updated.
+  BV nxt;
+  uint32_t nxt_id = kEmpty;
 
   for (;;) {
     // pop the first unchecked entry (the beam is kept sorted by (key, id))
@@ -433,8 +437,69 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     ++expansions;
 
     BV b;
-    b.load(a.blocks + (int64_t)p * a.block_bytes, lane);
+    if (p == nxt_id)
+      b = nxt;
+    else
+      b.load(a.blocks + (int64_t)p * a.block_bytes, lane);
+    nxt_id = kEmpty;
     const float dp = uni(exact_dist<DPL>(qv, b.x));
+
+    // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
+    const int S = b.fastscan(lut, lane);
+    const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
+    const uint32_t nb = (uint32_t)b.nb;
+    bool valid = (lane % LPN == 0) && b.nb >= 0;
+    if (valid) valid = !visited_contains<GV>(vis, nb);
+    appended += __popcll(ballot(valid));
+    if (size == ef && valid) {
+      const uint2 tail = beam[ef - 1];
+      valid = kv_less(est, nb, __uint_as_float(tail.x), tail.y & kIdMask);
+    }
+    const uint64_t V = ballot(valid);
+    const int nv = uni((int)__popcll(V));
+
+    // rank the candidates by (estimate, id)
+    int sidx = 0;
+    if (nv > 0) {
+      if (valid) ctmp[lanes_below(V)] = make_uint2(__float_as_uint(est), nb);
+      wave_sync();
+      if (valid) {
+        for (int t = 0; t < nv; ++t) {
+          const uint2 o = ctmp[t];
+          sidx += kv_less(__uint_as_float(o.x), o.y, est, nb);
+        }
+        csort[sidx] = make_uint2(__float_as_uint(est), nb);
+      }
+      wave_sync();
+    }
+
+    // the next pop: the smaller of the best candidate and the first unchecked
+    // old entry; prefetch its block unless it is already visited
+    {
+      float ok = __builtin_inff();
+      uint32_t oi = kEmpty;
+      for (int base = cursor; base < size; base += 64) {
+        const int i = base + lane;
+        const bool un = (i < size) && !(beam[i < size ? i : 0].y & kChecked);
+        const uint64_t m = ballot(un);
+        if (m) {
+          const uint2 e = beam[uni(base + first_lane(m))];
+          ok = uni(__uint_as_float(e.x));
+          oi = uni(e.y);
+          break;
+        }
+      }
+      if (nv > 0) {
+        const uint2 bc = csort[0];
+        const float bk = uni(__uint_as_float(bc.x));
+        const uint32_t bi = uni(bc.y);
+        if (oi == kEmpty || kv_less(bk, bi, ok, oi)) oi = bi;
+      }
+      if (oi != kEmpty && !visited_contains<GV>(vis, oi)) {
+        nxt.load(a.blocks + (int64_t)oi * a.block_bytes, lane);
+        nxt_id = oi;
+      }
+    }
 
     // implicit re-ranking: NN keeps the k smallest (distance, id) seen
     if (nnc < k || kv_less(dp, p, nn_wk, nn_wi)) {
@@ -473,33 +538,9 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       }
     }
 
-    // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
-    const int S = b.fastscan(lut, lane);
-    const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
-    const uint32_t nb = (uint32_t)b.nb;
-    bool valid = (lane % LPN == 0) && b.nb >= 0;
-    if (valid) valid = !visited_contains<GV>(vis, nb);
-    appended += __popcll(ballot(valid));
-    if (size == ef && valid) {
-      const uint2 tail = beam[ef - 1];
-      valid = kv_less(est, nb, __uint_as_float(tail.x), tail.y & kIdMask);
-    }
-    const uint64_t V = ballot(valid);
-    const int nv = uni((int)__popcll(V));
+
     if (nv == 0) continue;
 
-    // rank the candidates by (estimate, id)
-    if (valid) ctmp[lanes_below(V)] = make_uint2(__float_as_uint(est), nb);
-    wave_sync();
-    int sidx = 0;
-    if (valid) {
-      for (int t = 0; t < nv; ++t) {
-        const uint2 o = ctmp[t];
-        sidx += kv_less(__uint_as_float(o.x), o.y, est, nb);
-      }
-      csort[sidx] = make_uint2(__float_as_uint(est), nb);
-    }
-    wave_sync();
     // Old entry i moves up by cnt_i = #candidates strictly before it; the
     // candidate of rank r lands after lb_r = #old entries <= it, and since
     // cnt is non-decreasing, lb_r = i + 1 for cnt_i <= r < cnt_{i+1}.  Chunks
