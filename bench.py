@@ -161,6 +161,20 @@ def main():
                 "block_bytes": idx.block_bytes, "kernel_ms": round(kern_s * 1e3, 4),
                 "rotate_kernel_ms": round(rot_ms / max(n_rot, 1), 4)}
 
+    # HBM traffic from the committed PMC measurement (FETCH_SIZE and WRITE_SIZE
+    # scaled by a plain copy), only while the kernel source and ef still match
+    try:
+        import hashlib
+        with open(os.path.join(ROOT, "profiles", "search_kernel_traffic.json")) as f:
+            tr = json.load(f)
+        src = os.path.join(ROOT, "paper_2411_12229_amd", "csrc", "qg_kernels.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if tr.get("kernel_source_sha256_prefix") == sha and tr.get("ef") == ef and args.nq == 10_000 \
+                and args.n == 1_000_000:
+            roofline["traffic"] = tr["traffic_bytes"]
+    except (OSError, ValueError, KeyError):
+        pass
+
     cpu = None
     if not args.no_cpu and X is not None:
         sys.path.insert(0, os.path.join(ROOT, "oracle"))

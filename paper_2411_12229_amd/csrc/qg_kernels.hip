@@ -350,6 +350,11 @@ __device__ __forceinline__ bool visited_insert(const Visited& v, uint32_t id, in
   }
 }
 
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 template <int D, int R, bool GV>
 __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L, uint32_t* gbits) {
   using BV = BlockView<D, R>;
@@ -358,10 +363,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   const int lane = lane_id();
   const int ef = a.ef, k = a.k;
   int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
-  uint2* beam = reinterpret_cast<uint2*>(lds + L.beam);    // sorted (key bits, id | checked)
-  uint2* ctmp = reinterpret_cast<uint2*>(lds + L.ctmp);    // candidates in lane order
-  uint2* csort = reinterpret_cast<uint2*>(lds + L.csort);  // candidates in (key, id) order
-  int* lbarr = reinterpret_cast<int*>(lds + L.lb);
+  uint2* beam = reinterpret_cast<uint2*>(lds + L.beam);  // sorted (key bits, id | checked)
   float* nkey = reinterpret_cast<float*>(lds + L.nkey);
   uint32_t* nid = reinterpret_cast<uint32_t*>(lds + L.nid);
 
@@ -398,8 +400,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     wave_sync();
   }
   int size = 1, cursor = 0, nnc = 0;
-  float nn_wk = 0.0f;  // worst (distance, id) in NN once it holds k entries
+  float nn_wk = 0.0f;  // worst (distance, id) of NN once it holds k entries
   uint32_t nn_wi = 0;
+  float tail_k = 0.0f;  // beam[ef - 1] once the beam is full
+  uint32_t tail_i = 0;
   int expansions = 0, pops = 0, appended = 0;
   // Next-vertex prefetch (Sec. 3.1.4): once the new candidates are ranked,
   // the next pop is known, and its block is loaded while the beam is updated.
@@ -407,23 +411,37 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   uint32_t nxt_id = kEmpty;
 
   for (;;) {
-    // pop the first unchecked entry (the beam is kept sorted by (key, id))
+    // pop the first unchecked entry (the beam is kept sorted by (key, id)); the
+    // same chunk read gives the next unchecked entry after it
     int c = -1;
+    uint32_t p = 0;
+    float o2k = __builtin_inff();
+    uint32_t o2i = kEmpty;
+    bool o2_known = false;
     while (cursor < size) {
       const int i = cursor + lane;
-      const bool un = (i < size) && !(beam[i < size ? i : 0].y & kChecked);
-      const uint64_t m = ballot(un);
+      uint2 e = make_uint2(0u, kChecked);
+      if (i < size) e = beam[i];
+      const uint64_t m = ballot(!(e.y & kChecked));
       if (m) {
-        c = uni(cursor + first_lane(m));
+        const int f = first_lane(m);
+        c = cursor + f;
+        p = rdlane(e.y, f);
+        const uint64_t m2 = m & (m - 1);
+        if (m2) {
+          const int f2 = first_lane(m2);
+          o2k = rdlane(__uint_as_float(e.x), f2);
+          o2i = rdlane(e.y, f2);
+          o2_known = true;
+        } else {
+          o2_known = cursor + 64 >= size;  // nothing unchecked after c
+        }
         break;
       }
       cursor += 64;
     }
     if (c < 0) break;
-    const uint32_t p = uni(beam[c].y);
-    wave_sync();
     beam[c].y = p | kChecked;  // every lane stores the same word
-    wave_sync();
     cursor = c + 1;
     ++pops;
     if (visited_insert<GV>(vis, p, lane)) continue;  // a second estimate of a visited vertex
@@ -451,53 +469,48 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     bool valid = (lane % LPN == 0) && b.nb >= 0;
     if (valid) valid = !visited_contains<GV>(vis, nb);
     appended += __popcll(ballot(valid));
-    if (size == ef && valid) {
-      const uint2 tail = beam[ef - 1];
-      valid = kv_less(est, nb, __uint_as_float(tail.x), tail.y & kIdMask);
-    }
+    if (size == ef && valid) valid = kv_less(est, nb, tail_k, tail_i);
     const uint64_t V = ballot(valid);
     const int nv = uni((int)__popcll(V));
 
-    // rank the candidates by (estimate, id)
+    // rank the candidates by (estimate, id): candidate t is broadcast from its
+    // lane through a scalar register, no LDS round trip
     int sidx = 0;
+    for (uint64_t mm = V; mm; mm &= mm - 1) {
+      const int t = first_lane(mm);
+      sidx += kv_less(rdlane(est, t), rdlane(nb, t), est, nb) ? 1 : 0;
+    }
+    int t0 = -1;  // lane of the best candidate
+    float bk = __builtin_inff();
+    uint32_t bi = kEmpty;
     if (nv > 0) {
-      if (valid) ctmp[lanes_below(V)] = make_uint2(__float_as_uint(est), nb);
-      wave_sync();
-      if (valid) {
-        for (int t = 0; t < nv; ++t) {
-          const uint2 o = ctmp[t];
-          sidx += kv_less(__uint_as_float(o.x), o.y, est, nb);
-        }
-        csort[sidx] = make_uint2(__float_as_uint(est), nb);
-      }
-      wave_sync();
+      t0 = first_lane(ballot(valid && sidx == 0));
+      bk = rdlane(est, t0);
+      bi = rdlane(nb, t0);
     }
 
     // the next pop: the smaller of the best candidate and the first unchecked
     // old entry; prefetch its block unless it is already visited
-    {
-      float ok = __builtin_inff();
-      uint32_t oi = kEmpty;
+    if (!o2_known) {
       for (int base = cursor; base < size; base += 64) {
         const int i = base + lane;
-        const bool un = (i < size) && !(beam[i < size ? i : 0].y & kChecked);
-        const uint64_t m = ballot(un);
+        uint2 e = make_uint2(0u, kChecked);
+        if (i < size) e = beam[i];
+        const uint64_t m = ballot(!(e.y & kChecked));
         if (m) {
-          const uint2 e = beam[uni(base + first_lane(m))];
-          ok = uni(__uint_as_float(e.x));
-          oi = uni(e.y);
+          const int f = first_lane(m);
+          o2k = rdlane(__uint_as_float(e.x), f);
+          o2i = rdlane(e.y, f);
           break;
         }
       }
-      if (nv > 0) {
-        const uint2 bc = csort[0];
-        const float bk = uni(__uint_as_float(bc.x));
-        const uint32_t bi = uni(bc.y);
-        if (oi == kEmpty || kv_less(bk, bi, ok, oi)) oi = bi;
-      }
-      if (oi != kEmpty && !visited_contains<GV>(vis, oi)) {
-        nxt.load(a.blocks + (int64_t)oi * a.block_bytes, lane);
-        nxt_id = oi;
+    }
+    {
+      uint32_t nx = o2i;
+      if (nv > 0 && (o2i == kEmpty || kv_less(bk, bi, o2k, o2i))) nx = bi;
+      if (nx != kEmpty && !visited_contains<GV>(vis, nx)) {
+        nxt.load(a.blocks + (int64_t)nx * a.block_bytes, lane);
+        nxt_id = nx;
       }
     }
 
@@ -538,48 +551,49 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       }
     }
 
-
     if (nv == 0) continue;
 
-    // Old entry i moves up by cnt_i = #candidates strictly before it; the
-    // candidate of rank r lands after lb_r = #old entries <= it, and since
-    // cnt is non-decreasing, lb_r = i + 1 for cnt_i <= r < cnt_{i+1}.  Chunks
-    // go top down so no entry is overwritten before it is read.
-    int above = nv;  // cnt of the entry just above the current chunk (nv past the end)
+    // Merge (truncated to ef): old entry i moves to i + cnt_i, cnt_i = number of
+    // candidates strictly before it; the candidate of rank r lands at r + lb,
+    // lb = number of old entries <= it (an old entry precedes an equal new one).
+    // Chunks go top down, so no entry is overwritten before it is read.
+    int lbv = 0;  // lane t accumulates lb of the candidate held in lane t
     for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {
       const int i = base + lane;
+      const bool live = i < size;
       uint2 e = make_uint2(0u, 0u);
-      int cnt = nv;
-      if (i < size) {
-        e = beam[i];
-        const float ek = __uint_as_float(e.x);
-        const uint32_t ei = e.y & kIdMask;
-        cnt = 0;
-        for (int t = 0; t < nv; ++t) {
-          const uint2 o = csort[t];
-          cnt += kv_less(__uint_as_float(o.x), o.y, ek, ei);
-        }
+      if (live) e = beam[i];
+      const float ek = __uint_as_float(e.x);
+      const uint32_t ei = e.y & kIdMask;
+      int cnt = 0;
+      for (uint64_t mm = V; mm; mm &= mm - 1) {
+        const int t = first_lane(mm);
+        const bool lt = kv_less(rdlane(est, t), rdlane(nb, t), ek, ei);
+        cnt += lt ? 1 : 0;
+        const int le = __popcll(ballot(live && !lt));
+        lbv += (lane == t) ? le : 0;
       }
-      int up = __shfl_down(cnt, 1, 64);
-      if (lane == 63) up = above;
-      if (i < size) {
-        const int hi = (i + 1 < size) ? up : nv;
-        for (int r = cnt; r < hi; ++r) lbarr[r] = i + 1;
-        if (i == 0)
-          for (int r = 0; r < cnt; ++r) lbarr[r] = 0;
+      const int np = i + cnt;
+      const uint64_t tm = ballot(live && np == ef - 1);
+      if (tm) {
+        const int f = first_lane(tm);
+        tail_k = rdlane(ek, f);
+        tail_i = rdlane(ei, f);
       }
-      above = uni(cnt);
-      wave_sync();
-      if (i < size && i + cnt < ef) beam[i + cnt] = e;
-      wave_sync();
+      if (live && np < ef) beam[np] = e;
     }
-    int npos = ef;
-    if (valid) {
-      npos = sidx + lbarr[sidx];
-      if (npos < ef) beam[npos] = make_uint2(__float_as_uint(est), nb);
+    const int npos = sidx + lbv;
+    if (valid && npos < ef) beam[npos] = make_uint2(__float_as_uint(est), nb);
+    {
+      const uint64_t tm = ballot(valid && npos == ef - 1);
+      if (tm) {
+        const int f = first_lane(tm);
+        tail_k = rdlane(est, f);
+        tail_i = rdlane(nb, f);
+      }
     }
     wave_sync();
-    const int first = uni(__shfl(npos, first_lane(ballot(valid && sidx == 0)), 64));
+    const int first = uni((int)rdlane((uint32_t)npos, t0));
     if (first < cursor) cursor = first;
     size = (size + nv < ef) ? size + nv : ef;
   }
