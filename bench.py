@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--save-index", default="")
     ap.add_argument("--ef", type=int, default=0, help="skip the sweep and time this beam size")
     ap.add_argument("--load-index", default="", help="search a saved index (no recall: ground truth is not rebuilt)")
+    ap.add_argument("--no-learned-stop", action="store_true", help="time only the fixed-ef search")
+    ap.add_argument("--ls-ef", type=int, default=0, help="beam size for the learned stop (default: 2x the fixed ef)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -133,33 +135,88 @@ def main():
         chosen = (ef, rec, s)
     ef, rec, s = chosen
 
-    # timed region
-    for _ in range(args.warmup):
-        run(ef)
-    idx.timing(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for _ in range(args.steps):
-            idx.search(Qs, k, ef)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    idx.timing(False)
-    n_launch, search_ms = idx.timing_read(1)
-    n_rot, rot_ms = idx.timing_read(0)
-    ms_per_step = (t2 - t1) * 1e3 / args.steps
-    qps = args.nq * args.steps / (t2 - t1)
+    def timed(search_fn):
+        """W untimed warm-up steps, then K steps bracketed by synchronisation;
+        search-kernel launches are timed with HIP events on the library's stream."""
+        for _ in range(args.warmup):
+            search_fn()
+        stream.synchronize()
+        idx.timing(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(args.steps):
+                search_fn()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        idx.timing(False)
+        n_launch, search_ms = idx.timing_read(1)
+        n_rot, rot_ms = idx.timing_read(0)
+        return (args.nq * args.steps / (t2 - t1), (t2 - t1) * 1e3 / args.steps, search_ms / n_launch,
+                rot_ms / max(n_rot, 1))
 
+    def plain():
+        with torch.cuda.stream(stream):
+            idx.search(Qs, k, ef)
+
+    qps, ms_per_step, kern_ms, rot_ms = timed(plain)
     expansions = int(s[:, 0].sum())
     alg_bytes = expansions * idx.block_bytes + args.nq * (4 * D + 8 * k)
-    kern_s = search_ms / n_launch / 1e3
-    achieved = alg_bytes / kern_s
+    achieved = alg_bytes / (kern_ms / 1e3)
     roofline = {"bound": "hbm", "kernel": "search_kernel<128,32>", "achieved": round(achieved / 1e9, 1),
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": None,
                 "bytes_per_launch": alg_bytes, "expansions_per_launch": expansions,
-                "block_bytes": idx.block_bytes, "kernel_ms": round(kern_s * 1e3, 4),
-                "rotate_kernel_ms": round(rot_ms / max(n_rot, 1), 4)}
+                "block_bytes": idx.block_bytes, "kernel_ms": round(kern_ms, 4), "rotate_kernel_ms": round(rot_ms, 4)}
+    fixed = {"ef": ef, "recall@10": round(rec, 4), "qps": round(qps, 1), "ms_per_step": round(ms_per_step, 4),
+             "mean_expansions": round(expansions / args.nq, 2)}
+
+    # learned stop: trained on separately seeded queries, theta picked on a held-out part of them
+    ls_res = None
+    if not args.no_learned_stop and gt is not None:
+        from paper_2411_12229_amd import learned_stop
+        t0 = time.time()
+        _, Qtr = synth.gen_data(2, n=1, nq=20_000, qseed=synth.seed(2, "train"))
+        gt_tr, _ = synth.ground_truth(X, Qtr, k, device=dev)
+        Qtr_d, gt_tr_d = torch.from_numpy(Qtr).to(dev), torch.from_numpy(gt_tr).to(dev)
+        ls_ef = args.ls_ef or 2 * ef
+        t_min, t_every = 8, 4
+        with torch.cuda.stream(stream):
+            feat, lab = learned_stop.collect(idx, Qtr_d[:16_000].contiguous(), gt_tr_d[:16_000], k, ls_ef, t_min,
+                                             t_every)
+            model = learned_stop.train(feat, lab, epochs=6)
+            bits = learned_stop.export(model)
+            pick = learned_stop.pick_theta(idx, Qtr_d[16_000:].contiguous(), gt_tr_d[16_000:], bits, k, ls_ef,
+                                           t_min, t_every, target=args.target + 0.005)
+        stream.synchronize()
+        log(f"[bench] learned stop: {feat.shape[0]} trace points, trained in {time.time() - t0:.1f}s, theta {pick}")
+        if pick is not None:
+            theta = pick[0]
+            with torch.cuda.stream(stream):
+                ids_l, _, st_l, _ = idx.search_stop(Qs, k, ls_ef, bits, theta=theta, t_min=t_min, t_every=t_every,
+                                                    stats=True)
+            stream.synchronize()
+            rec_l = synth.recall(ids_l.cpu().numpy(), gt, k)
+            exp_l = int(st_l[:, 0].sum().item())
+
+            def stopped():
+                with torch.cuda.stream(stream):
+                    idx.search_stop(Qs, k, ls_ef, bits, theta=theta, t_min=t_min, t_every=t_every)
+
+            qps_l, ms_l, kern_l, _ = timed(stopped)
+            ls_res = {"ef": ls_ef, "theta": theta, "t_min": t_min, "t_every": t_every, "recall@10": round(rec_l, 4),
+                      "qps": round(qps_l, 1), "ms_per_step": round(ms_l, 4), "kernel_ms": round(kern_l, 4),
+                      "mean_expansions": round(exp_l / args.nq, 2), "trace_points": int(feat.shape[0]),
+                      "train_queries": 16_000, "theta_queries": 4_000}
+            log(f"[bench] learned stop ef={ls_ef} theta={theta}: recall@10={rec_l:.4f} {qps_l:,.0f} q/s "
+                f"(fixed ef={ef}: recall {rec:.4f} {qps:,.0f} q/s)")
+            if rec_l >= args.target and qps_l > qps:
+                qps, ms_per_step = qps_l, ms_l
+                achieved = (exp_l * idx.block_bytes + args.nq * (4 * D + 8 * k)) / (kern_l / 1e3)
+                roofline.update({"kernel": "search_kernel<128,32> with learned stop",
+                                 "achieved": round(achieved / 1e9, 1), "frac": round(achieved / HBM_PEAK, 4),
+                                 "bytes_per_launch": exp_l * idx.block_bytes + args.nq * (4 * D + 8 * k),
+                                 "expansions_per_launch": exp_l, "kernel_ms": round(kern_l, 4)})
 
     # HBM traffic from the committed PMC measurement (FETCH_SIZE and WRITE_SIZE
     # scaled by a plain copy), only while the kernel source and ef still match
@@ -200,9 +257,13 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"SIFT-shaped 1M x 128 fp32 integer-valued 1000-component mixture, R=32 index, "
-                               f"{args.nq} queries, k=10, fixed-ef search (learned stop not built)",
-                   "n": args.n, "d": D, "r": R, "nq": args.nq, "k": k, "ef": ef, "recall@10": round(rec, 4),
-                   "search": "fixed-ef", "graph": "k-NN + random long links (input generator)"},
+                               f"{args.nq} queries, k=10; value = the faster of fixed-ef and learned-stop search "
+                               f"with recall@10 >= {args.target}",
+                   "n": args.n, "d": D, "r": R, "nq": args.nq, "k": k,
+                   "search": "learned-stop" if roofline["kernel"].endswith("learned stop") else "fixed-ef",
+                   "graph": "k-NN + random long links (input generator)"},
+        "fixed_ef": fixed,
+        "learned_stop": ls_res,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,

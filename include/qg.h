@@ -88,6 +88,36 @@ int qg_search(const qg_index *idx, const float *queries, int64_t nq, int32_t k, 
 int qg_search_ex(const qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                  int32_t *out_ids, float *out_dists, int32_t *out_stats);
 
+/* Learned early stop (an addition beyond the paper, whose Algorithm 1 runs
+ * until the beam holds no unchecked entry).  After the t-th expansion, for
+ * t >= t_min with (t - t_min) divisible by t_every, a 16-64-64-1 ReLU MLP with
+ * bf16 parameters and fp32 arithmetic reads 16 features of the search state
+ * (expansions, pops, NN fill and distances relative to the entry, the next
+ * beam estimate relative to the k-th distance, beam fill, ...) and the query
+ * stops when its output exceeds theta.  Parameters (QG_STOP_MLP_PARAMS bf16
+ * bit patterns, device memory): W1[64][16], b1[64], W2[64][64], b2[64],
+ * W3[64], b3.  With mlp == NULL nothing stops early and only the trace is
+ * written: features [nq][trace_max][16] (fp32), NN ids [nq][trace_max][k],
+ * MLP output [nq][trace_max] (NaN without a model) and the number of
+ * evaluation points recorded per query [nq] -- the training data. */
+#define QG_STOP_MLP_PARAMS (64 * 16 + 64 + 64 * 64 + 64 + 64 + 1)
+
+typedef struct qg_stop_params {
+  const uint16_t *mlp; /* device, QG_STOP_MLP_PARAMS values, 16-byte aligned; NULL = no early stop */
+  float theta;
+  int32_t t_min;   /* >= 1 */
+  int32_t t_every; /* >= 1 */
+  int32_t trace_max;      /* evaluation points recorded per query; 0 = no trace */
+  float *trace_features;  /* device, nullable when trace_max == 0 */
+  int32_t *trace_nn;
+  float *trace_out;
+  int32_t *trace_count;
+} qg_stop_params;
+
+/* qg_search_ex with the learned stop (stop != NULL) described above. */
+int qg_search_stop(const qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                   const qg_stop_params *stop, int32_t *out_ids, float *out_dists, int32_t *out_stats);
+
 /* out[n][d] = M in[n][d] for the index's rotation M (Eq. rotation), on the
  * matrix cores: fp64 products accumulated over j ascending, rounded once to
  * fp32.  This is the first step of qg_search, exposed for checking. */

@@ -58,6 +58,12 @@ def lib():
         L.qgo_search.argtypes = [P, i64, ctypes.c_int, ctypes.c_int, i32, P, P, i64, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, P, P, P, ctypes.c_int]
         L.qgo_search.restype = ctypes.c_int
+        L.qgo_search_ls.argtypes = [P, i64, ctypes.c_int, ctypes.c_int, i32, P, P, i64, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, P, P, P, ctypes.c_int, P, ctypes.c_float, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, P, P, P, P]
+        L.qgo_search_ls.restype = ctypes.c_int
+        L.qgo_ls_mlp.argtypes = [P, P]
+        L.qgo_ls_mlp.restype = ctypes.c_float
         L.qgo_max_threads.argtypes = []
         L.qgo_max_threads.restype = ctypes.c_int
         L.qgo_build_graph.argtypes = [P, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, i32, P, P,
@@ -148,6 +154,45 @@ def search(blocks: np.ndarray, D: int, R: int, entry: int, M: np.ndarray, Q: np.
     if rc != 0:
         raise RuntimeError(f"qgo_search failed: {rc}")
     return (ids, dists, stats) if with_stats else (ids, dists)
+
+
+LS_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def search_ls(blocks, D, R, entry, M, Q, k, ef, w=None, theta=0.0, t_min=8, t_every=4, max_evals=0,
+              flags=0, nthreads=0):
+    """Algorithm 1 with the learned stop (w: uint16 bf16 parameters or None) and
+    an optional trace.  Returns (ids, dists, stats, trace) with trace =
+    (features [nq,max_evals,16], nn ids [nq,max_evals,k], mlp out [nq,max_evals], count [nq]) or None."""
+    blocks = _c(blocks, np.uint8)
+    M = _c(M, np.float32)
+    Q = _c(np.atleast_2d(Q), np.float32)
+    nq, N = Q.shape[0], blocks.shape[0]
+    ids = np.zeros((nq, k), np.int32)
+    dists = np.zeros((nq, k), np.float32)
+    stats = np.zeros((nq, 4), np.int64)
+    wp = None
+    if w is not None:
+        w = _c(w, np.uint16)
+        assert w.size == LS_PARAMS
+        wp = _p(w)
+    me = max(max_evals, 0)
+    tf = np.zeros((nq, max(me, 1), 16), np.float32)
+    tn = np.zeros((nq, max(me, 1), k), np.int32)
+    to = np.zeros((nq, max(me, 1)), np.float32)
+    tc = np.zeros(nq, np.int32)
+    rc = lib().qgo_search_ls(_p(blocks), N, D, R, int(entry), _p(M), _p(Q), nq, k, ef, flags, _p(ids), _p(dists),
+                             _p(stats), nthreads, wp, float(theta), t_min, t_every, me, _p(tf), _p(tn), _p(to),
+                             _p(tc))
+    if rc != 0:
+        raise RuntimeError(f"qgo_search_ls failed: {rc}")
+    return ids, dists, stats, ((tf, tn, to, tc) if me else None)
+
+
+def ls_mlp(w, f) -> float:
+    w = _c(w, np.uint16)
+    f = _c(f, np.float32)
+    return float(lib().qgo_ls_mlp(_p(w), _p(f)))
 
 
 def build_graph(X: np.ndarray, R: int, EF: int, t: int, M: np.ndarray, entry: int, G0: np.ndarray,

@@ -259,6 +259,90 @@ void qgo_estimate(const uint8_t *blocks, int D, int R, const float *q, const flo
 
 /* --------------------------------------------------------------- search */
 
+/* ------------------------------------------------------- learned stop */
+
+/* Learned early stop (an extension beyond the paper; the paper's Algorithm 1
+ * runs until the beam has no unchecked entry).  After the t-th expansion, for
+ * t >= t_min with (t - t_min) divisible by t_every, 16 features of the search
+ * state feed a 16-64-64-1 ReLU MLP with bf16 parameters and fp32 arithmetic;
+ * the search stops when its output exceeds theta.  Canonical arithmetic (the
+ * device kernel uses the same order): hidden unit j = fma chain over its
+ * inputs in ascending order starting from its bias, then ReLU (x > 0 ? x : 0);
+ * output = butterfly sum (p[l] + p[l^s], s = 32 .. 1) of w3[j] * h2[j], plus
+ * the output bias.  Parameter layout (bf16 bit patterns): W1[64][16], b1[64],
+ * W2[64][64], b2[64], W3[64], b3. */
+#define QGO_LS_PARAMS (64 * 16 + 64 + 64 * 64 + 64 + 64 + 1)
+
+typedef struct {
+  const uint16_t *w; /* NULL: never stop early */
+  float theta;
+  int t_min, t_every;
+  int max_evals; /* trace capacity per query (0: no trace) */
+  float *tr_feat; /* [max_evals][16] */
+  int32_t *tr_nn; /* [max_evals][k] */
+  float *tr_out;  /* [max_evals] (MLP output, NaN without a model) */
+  int32_t *tr_count;
+} qgo_ls;
+
+static float bf16f(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+static float ratio(float a, float b) { return b > 0.0f ? a / b : 0.0f; }
+
+static float clamp8(float x) { return x < 0.0f ? 0.0f : (x > 8.0f ? 8.0f : x); }
+
+/* Search-state features at an evaluation point.  de: entry distance; nn1,
+ * nnk: best and last of NN; bf: estimate of the next beam entry to pop (+inf
+ * if none); dp: exact distance of the vertex just expanded; app: neighbours
+ * appended by that expansion; since: expansions since NN last changed. */
+static void ls_features(float *f, int E, int P, int nnc, int k, int since, float de, float nn1, float nnk, float bf,
+                        int size, int ef, float dp, int app, int R) {
+  f[0] = (float)E / 64.0f;
+  f[1] = (float)P / 64.0f;
+  f[2] = (float)nnc / (float)k;
+  f[3] = (float)since / 16.0f;
+  f[4] = ratio(nn1, de);
+  f[5] = ratio(nnk, de);
+  f[6] = ratio(bf, nnk);
+  f[7] = ratio(bf, nn1);
+  f[8] = (float)size / (float)ef;
+  f[9] = ratio(dp, nnk);
+  f[10] = (float)app / (float)R;
+  f[11] = ratio(nnk - nn1, nnk);
+  f[12] = (float)ef / 256.0f;
+  f[13] = ratio(bf, de);
+  f[14] = (float)E / (float)ef;
+  f[15] = 1.0f;
+  for (int i = 0; i < 16; ++i) f[i] = clamp8(f[i]);
+}
+
+static float ls_mlp(const uint16_t *w, const float *f) {
+  const uint16_t *W1 = w, *b1 = W1 + 64 * 16, *W2 = b1 + 64, *b2 = W2 + 64 * 64, *W3 = b2 + 64, *b3 = W3 + 64;
+  float h1[64], h2[64], p[64], t[64];
+  for (int j = 0; j < 64; ++j) {
+    float acc = bf16f(b1[j]);
+    for (int i = 0; i < 16; ++i) acc = fmaf(bf16f(W1[j * 16 + i]), f[i], acc);
+    h1[j] = acc > 0.0f ? acc : 0.0f;
+  }
+  for (int j = 0; j < 64; ++j) {
+    float acc = bf16f(b2[j]);
+    for (int i = 0; i < 64; ++i) acc = fmaf(bf16f(W2[j * 64 + i]), h1[i], acc);
+    h2[j] = acc > 0.0f ? acc : 0.0f;
+  }
+  for (int j = 0; j < 64; ++j) p[j] = bf16f(W3[j]) * h2[j];
+  for (int sft = 32; sft >= 1; sft >>= 1) {
+    for (int l = 0; l < 64; ++l) t[l] = p[l] + p[l ^ sft];
+    memcpy(p, t, sizeof p);
+  }
+  return p[0] + bf16f(b3[0]);
+}
+
+float qgo_ls_mlp(const uint16_t *w, const float *f) { return ls_mlp(w, f); }
+
 typedef struct {
   float key;
   int32_t id;
@@ -285,7 +369,7 @@ static int less_kv(float ka, int32_t ia, float kb, int32_t ib) { return ka < kb 
  * stats (nullable): [expansions, pops, appended, 0]. */
 static void search_one(const uint8_t *blocks, int64_t N, int D, int R, int32_t entry, const float *M, const float *q,
                        int k, int ef, int flags, int32_t *ids, float *dists, int64_t *stats, uint8_t *visited,
-                       uint8_t *seen, int32_t *touched) {
+                       uint8_t *seen, int32_t *touched, const qgo_ls *ls, int64_t qi) {
   int64_t B = qgo_block_bytes(D, R);
   float *qrot = (float *)malloc(sizeof(float) * D);
   int32_t *qs = (int32_t *)malloc(sizeof(int32_t) * D);
@@ -302,7 +386,9 @@ static void search_one(const uint8_t *blocks, int64_t N, int D, int R, int32_t e
 
   int n = 0, nn = 0;
   int64_t expansions = 0, pops = 0, appended = 0;
-  S[n].key = qgo_exact_dist(q, blk_raw(blocks + (int64_t)entry * B), D);
+  int since = 0, nevals = 0;
+  const float de = qgo_exact_dist(q, blk_raw(blocks + (int64_t)entry * B), D);
+  S[n].key = de;
   S[n].id = entry;
   S[n].checked = 0;
   ++n;
@@ -328,7 +414,9 @@ static void search_one(const uint8_t *blocks, int64_t N, int D, int R, int32_t e
     const uint8_t *blk = blocks + (int64_t)p * B;
     float dp = qgo_exact_dist(q, blk_raw(blk), D);
     /* update NN with (dp, p) */
+    ++since;
     if (nn < k || less_kv(dp, p, nn_d[nn - 1], nn_i[nn - 1])) {
+      since = 0;
       int pos = nn < k ? nn : k - 1;
       while (pos > 0 && less_kv(dp, p, nn_d[pos - 1], nn_i[pos - 1])) {
         nn_d[pos] = nn_d[pos - 1];
@@ -344,6 +432,7 @@ static void search_one(const uint8_t *blocks, int64_t N, int D, int R, int32_t e
     const float *fa = blk_fadd(blk, D, R), *fr = blk_fres(blk, D, R);
     const int32_t *nb = blk_nbr(blk, D, R);
     int n_before = n;
+    int64_t app0 = appended;
     for (int j = 0; j < R; ++j) {
       int32_t o = nb[j];
       if (o < 0 || visited[o]) continue;
@@ -385,6 +474,26 @@ static void search_one(const uint8_t *blocks, int64_t N, int D, int R, int32_t e
       memcpy(S, merged, sizeof(beam_entry) * (size_t)w);
       n = w;
     }
+    /* learned stop: evaluation point after this expansion */
+    if (ls && expansions >= ls->t_min && (expansions - ls->t_min) % ls->t_every == 0) {
+      float bf = INFINITY;
+      for (int i = 0; i < n; ++i)
+        if (!S[i].checked) {
+          bf = S[i].key;
+          break;
+        }
+      float f[16];
+      ls_features(f, (int)expansions, (int)pops, nn, k, since, de, nn_d[0], nn_d[nn - 1], bf, n, ef, dp,
+                  (int)(appended - app0), R);
+      float out = ls->w ? ls_mlp(ls->w, f) : NAN;
+      if (ls->max_evals > 0 && nevals < ls->max_evals) {
+        memcpy(ls->tr_feat + (qi * ls->max_evals + nevals) * 16, f, sizeof f);
+        for (int i = 0; i < k; ++i) ls->tr_nn[(qi * ls->max_evals + nevals) * k + i] = i < nn ? nn_i[i] : -1;
+        ls->tr_out[qi * ls->max_evals + nevals] = out;
+      }
+      ++nevals;
+      if (ls->w && out > ls->theta) break;
+    }
     if (n > ef) n = ef;
   }
   for (int i = 0; i < k; ++i) {
@@ -397,6 +506,7 @@ static void search_one(const uint8_t *blocks, int64_t N, int D, int R, int32_t e
     stats[2] = appended;
     stats[3] = 0;
   }
+  if (ls && ls->max_evals > 0) ls->tr_count[qi] = nevals < ls->max_evals ? nevals : ls->max_evals;
   for (int64_t i = 0; i < ntouched; ++i) visited[touched[i]] = 0;
   if (seen)
     for (int64_t i = 0; i < nseen; ++i) seen[seen_list[i]] = 0;
@@ -412,8 +522,9 @@ static void search_one(const uint8_t *blocks, int64_t N, int D, int R, int32_t e
 
 /* Search nq queries Q[nq][D]; ids/dists are [nq][k]; stats [nq][4] or NULL.
  * Queries are independent; OpenMP spreads them over nthreads (0 = default). */
-int qgo_search(const uint8_t *blocks, int64_t N, int D, int R, int32_t entry, const float *M, const float *Q,
-               int64_t nq, int k, int ef, int flags, int32_t *ids, float *dists, int64_t *stats, int nthreads) {
+static int search_all(const uint8_t *blocks, int64_t N, int D, int R, int32_t entry, const float *M, const float *Q,
+                      int64_t nq, int k, int ef, int flags, int32_t *ids, float *dists, int64_t *stats, int nthreads,
+                      const qgo_ls *ls) {
   if (N <= 0 || D <= 0 || D % 8 || R <= 0 || k <= 0 || ef <= 0 || nq < 0 || entry < 0 || entry >= N) return -1;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -431,13 +542,30 @@ int qgo_search(const uint8_t *blocks, int64_t N, int D, int R, int32_t entry, co
 #pragma omp for schedule(dynamic, 1)
       for (int64_t i = 0; i < nq; ++i)
         search_one(blocks, N, D, R, entry, M, Q + i * D, k, ef, flags, ids + i * k, dists + i * k,
-                   stats ? stats + 4 * i : NULL, visited, seen, touched);
+                   stats ? stats + 4 * i : NULL, visited, seen, touched, ls, i);
     }
     free(visited);
     free(seen);
     free(touched);
   }
   return rc;
+}
+
+int qgo_search(const uint8_t *blocks, int64_t N, int D, int R, int32_t entry, const float *M, const float *Q,
+               int64_t nq, int k, int ef, int flags, int32_t *ids, float *dists, int64_t *stats, int nthreads) {
+  return search_all(blocks, N, D, R, entry, M, Q, nq, k, ef, flags, ids, dists, stats, nthreads, NULL);
+}
+
+/* Algorithm 1 with the learned stop (w may be NULL: plain search) and an
+ * optional trace of the features, NN ids and MLP output at every evaluation
+ * point (max_evals per query; tr_* may be NULL when max_evals is 0). */
+int qgo_search_ls(const uint8_t *blocks, int64_t N, int D, int R, int32_t entry, const float *M, const float *Q,
+                  int64_t nq, int k, int ef, int flags, int32_t *ids, float *dists, int64_t *stats, int nthreads,
+                  const uint16_t *w, float theta, int t_min, int t_every, int max_evals, float *tr_feat,
+                  int32_t *tr_nn, float *tr_out, int32_t *tr_count) {
+  if (t_min < 1 || t_every < 1 || max_evals < 0) return -1;
+  qgo_ls ls = {w, theta, t_min, t_every, max_evals, tr_feat, tr_nn, tr_out, tr_count};
+  return search_all(blocks, N, D, R, entry, M, Q, nq, k, ef, flags, ids, dists, stats, nthreads, &ls);
 }
 
 int qgo_max_threads(void) {

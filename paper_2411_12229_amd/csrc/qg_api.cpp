@@ -374,8 +374,8 @@ int qg_rotate(const qg_index* idx, const float* in, int64_t n, float* out) {
   return QG_OK;
 }
 
-int qg_search_ex(const qg_index* cidx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
-                 int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+int qg_search_stop(const qg_index* cidx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                   const qg_stop_params* stop, int32_t* out_ids, float* out_dists, int32_t* out_stats) {
   qg_index* idx = const_cast<qg_index*>(cidx);
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (nq < 0) return fail(QG_EINVAL, "nq < 0");
@@ -383,6 +383,12 @@ int qg_search_ex(const qg_index* cidx, const float* queries, int64_t nq, int32_t
   if (k > QG_MAX_K || ef > QG_MAX_EF) return fail(QG_EUNSUPPORTED, "k or ef above the supported maximum");
   if (flags & ~(QG_SEARCH_NO_ME | QG_SEARCH_SMALL_HASH)) return fail(QG_EINVAL, "unknown flags");
   if (flags & QG_SEARCH_NO_ME) return fail(QG_EUNSUPPORTED, "QG_SEARCH_NO_ME is not supported on the device");
+  if (stop) {
+    if (stop->t_min < 1 || stop->t_every < 1 || stop->trace_max < 0) return fail(QG_EINVAL, "bad stop parameters");
+    if (stop->trace_max > 0 && (!stop->trace_features || !stop->trace_nn || !stop->trace_out || !stop->trace_count))
+      return fail(QG_EINVAL, "NULL trace array");
+    if (reinterpret_cast<uintptr_t>(stop->mlp) % 16) return fail(QG_EINVAL, "MLP parameters must be 16-byte aligned");
+  }
   if (nq == 0) return QG_OK;
   if (nq > 0x7fffffffLL) return fail(QG_EINVAL, "nq too large");
   if (!queries || !out_ids || !out_dists) return fail(QG_EINVAL, "NULL array");
@@ -418,6 +424,18 @@ int qg_search_ex(const qg_index* cidx, const float* queries, int64_t nq, int32_t
   a.overflow_list = idx->overflow;
   a.fb_bits = idx->fb_bits;
   a.fb_words = idx->fb_words;
+  const bool ls = stop != nullptr;
+  if (ls) {
+    a.ls_w = stop->mlp;
+    a.ls_theta = stop->theta;
+    a.ls_t_min = stop->t_min;
+    a.ls_t_every = stop->t_every;
+    a.tr_max = stop->trace_max;
+    a.tr_feat = stop->trace_features;
+    a.tr_nn = stop->trace_nn;
+    a.tr_out = stop->trace_out;
+    a.tr_count = stop->trace_count;
+  }
 
   const qgl::SearchLds L = qgl::search_lds(idx->D, idx->R, ef_cap, 1 << hbits, k_cap);
   const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
@@ -425,7 +443,7 @@ int qg_search_ex(const qg_index* cidx, const float* queries, int64_t nq, int32_t
   int wpb = 4;
   while (wpb > 1 && (size_t)wpb * L.total > lds_cap) wpb >>= 1;
   if ((size_t)L.total > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
-  int occ = qgk::search_occupancy(idx->D, idx->R, false, wpb, (size_t)wpb * L.total);
+  int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, wpb, (size_t)wpb * L.total);
   if (occ <= 0) occ = 1;
   int64_t want = (nq + wpb - 1) / wpb;
   int grid = (int)std::min<int64_t>(want, (int64_t)occ * 256);
@@ -435,12 +453,17 @@ int qg_search_ex(const qg_index* cidx, const float* queries, int64_t nq, int32_t
           "rotate queries");
   if ((rc = record(idx, 0, false))) return rc;
   if ((rc = record(idx, 1, true))) return rc;
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, a, grid, wpb, (size_t)wpb * L.total, idx->stream), "search");
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, a, grid, wpb, (size_t)wpb * L.total, idx->stream), "search");
   if ((rc = record(idx, 1, false))) return rc;
   // overflow pass: one wavefront per workgroup, one bitset each
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, a, idx->fb_slots, 1, (size_t)Lf.total, idx->stream),
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, a, idx->fb_slots, 1, (size_t)Lf.total, idx->stream),
           "search overflow pass");
   return QG_OK;
+}
+
+int qg_search_ex(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                 int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+  return qg_search_stop(idx, queries, nq, k, ef, flags, nullptr, out_ids, out_dists, out_stats);
 }
 
 int qg_search(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t* out_ids,

@@ -23,6 +23,15 @@ struct SearchArgs {
   int32_t* overflow_list; // [nq]
   uint32_t* fb_bits;      // overflow pass: one N-bit set per wavefront
   int64_t fb_words;       // 32-bit words per set
+  // learned stop (search kernels instantiated with LS = true)
+  const uint16_t* ls_w;   // MLP parameters (bf16 bits) or null: evaluate and trace only
+  float ls_theta;
+  int ls_t_min, ls_t_every;
+  int tr_max;             // evaluation points traced per query (0 = no trace)
+  float* tr_feat;         // [nq][tr_max][16]
+  int32_t* tr_nn;         // [nq][tr_max][k]
+  float* tr_out;          // [nq][tr_max]
+  int32_t* tr_count;      // [nq]
 };
 
 struct EstimateArgs {
@@ -41,9 +50,9 @@ hipError_t launch_rotate(const float* in, int64_t n, int D, const float* M, floa
                          hipStream_t st);
 hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, const int32_t* G, int R,
                          uint8_t* blocks, int64_t B, hipStream_t st);
-hipError_t launch_search(int D, int R, bool overflow_pass, const SearchArgs& a, int grid, int wpb, size_t lds,
-                         hipStream_t st);
-int search_occupancy(int D, int R, bool overflow_pass, int wpb, size_t lds);
+hipError_t launch_search(int D, int R, bool overflow_pass, bool learned_stop, const SearchArgs& a, int grid, int wpb,
+                         size_t lds, hipStream_t st);
+int search_occupancy(int D, int R, bool overflow_pass, bool learned_stop, int wpb, size_t lds);
 hipError_t launch_estimate(int D, int R, const EstimateArgs& a, int64_t nq, hipStream_t st);
 
 }  // namespace qgk

@@ -350,12 +350,87 @@ __device__ __forceinline__ bool visited_insert(const Visited& v, uint32_t id, in
   }
 }
 
+
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
 __device__ __forceinline__ float rdlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-template <int D, int R, bool GV>
+// ------------------------------------------------------------ learned stop
+
+// Learned early stop (an extension beyond the paper, whose Algorithm 1 runs
+// until no unchecked beam entry is left): after the t-th expansion, for
+// t >= t_min with (t - t_min) divisible by t_every, 16 state features feed a
+// 16-64-64-1 ReLU MLP (bf16 parameters, fp32 arithmetic); the query stops when
+// the output exceeds theta.  Hidden unit j runs on lane j as an fma chain over
+// its inputs in ascending order from its bias; the output is the butterfly sum
+// of w3[j] * h2[j] plus the output bias.  Parameter layout: W1[64][16], b1[64],
+// W2[64][64], b2[64], W3[64], b3.
+constexpr int kLsW1 = 0, kLsB1 = 64 * 16, kLsW2 = kLsB1 + 64, kLsB2 = kLsW2 + 64 * 64, kLsW3 = kLsB2 + 64,
+              kLsB3 = kLsW3 + 64;
+
+__device__ __forceinline__ float bf16lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+__device__ __forceinline__ float bf16at(const uint16_t* w, int i) { return __uint_as_float((uint32_t)w[i] << 16); }
+__device__ __forceinline__ float ratio(float a, float b) { return b > 0.0f ? a / b : 0.0f; }
+__device__ __forceinline__ float clamp8(float x) { return x < 0.0f ? 0.0f : (x > 8.0f ? 8.0f : x); }
+
+struct StopFeatures {
+  float f[16];
+  __device__ __forceinline__ void compute(int E, int P, int nnc, int k, int since, float de, float nn1, float nnk,
+                                          float bf, int size, int ef, float dp, int app, int R) {
+    f[0] = (float)E / 64.0f;
+    f[1] = (float)P / 64.0f;
+    f[2] = (float)nnc / (float)k;
+    f[3] = (float)since / 16.0f;
+    f[4] = ratio(nn1, de);
+    f[5] = ratio(nnk, de);
+    f[6] = ratio(bf, nnk);
+    f[7] = ratio(bf, nn1);
+    f[8] = (float)size / (float)ef;
+    f[9] = ratio(dp, nnk);
+    f[10] = (float)app / (float)R;
+    f[11] = ratio(nnk - nn1, nnk);
+    f[12] = (float)ef / 256.0f;
+    f[13] = ratio(bf, de);
+    f[14] = (float)E / (float)ef;
+    f[15] = 1.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = clamp8(f[i]);
+  }
+};
+
+__device__ __forceinline__ float stop_mlp(const uint16_t* __restrict__ w, const StopFeatures& F, int lane) {
+  // layer 1: this lane's row of W1 (16 bf16 = two 16-byte loads)
+  const uint4* r1 = reinterpret_cast<const uint4*>(w + kLsW1 + lane * 16);
+  const uint4 a0 = r1[0], a1 = r1[1];
+  const uint32_t wr[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+  float acc = bf16at(w, kLsB1 + lane);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    acc = __builtin_fmaf(bf16lo(wr[i]), F.f[2 * i], acc);
+    acc = __builtin_fmaf(bf16hi(wr[i]), F.f[2 * i + 1], acc);
+  }
+  const float h1 = acc > 0.0f ? acc : 0.0f;
+  // layer 2: every lane needs all 64 h1 values; they come through scalar registers
+  const uint4* r2 = reinterpret_cast<const uint4*>(w + kLsW2 + lane * 64);
+  acc = bf16at(w, kLsB2 + lane);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const uint4 v = r2[c];
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      acc = __builtin_fmaf(bf16lo(u[h]), rdlane(h1, 8 * c + 2 * h), acc);
+      acc = __builtin_fmaf(bf16hi(u[h]), rdlane(h1, 8 * c + 2 * h + 1), acc);
+    }
+  }
+  const float h2 = acc > 0.0f ? acc : 0.0f;
+  const float pr = bf16at(w, kLsW3 + lane) * h2;
+  return uni(butterfly_f(pr) + bf16at(w, kLsB3));
+}
+
+template <int D, int R, bool GV, bool LS>
 __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L, uint32_t* gbits) {
   using BV = BlockView<D, R>;
   constexpr int DPL = BV::DPL;
@@ -392,23 +467,25 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   const float delta = build_lut<D, R>(a.qrot + q * D, lut);
 
   // S starts with the entry keyed by its exact distance (reading S13).
+  float de;
   {
     BV e;
     e.load(a.blocks + (int64_t)a.entry * a.block_bytes, lane);
-    const float de = uni(exact_dist<DPL>(qv, e.x));
+    de = uni(exact_dist<DPL>(qv, e.x));
     beam[0] = make_uint2(__float_as_uint(de), (uint32_t)a.entry);
     wave_sync();
   }
   int size = 1, cursor = 0, nnc = 0;
   float nn_wk = 0.0f;  // worst (distance, id) of NN once it holds k entries
   uint32_t nn_wi = 0;
-  float tail_k = 0.0f;  // beam[ef - 1] once the beam is full
-  uint32_t tail_i = 0;
+  float tail_k = de;  // beam[ef - 1] whenever the beam is full (from the start when ef = 1)
+  uint32_t tail_i = (uint32_t)a.entry;
   int expansions = 0, pops = 0, appended = 0;
   // Next-vertex prefetch (Sec. 3.1.4): once the new candidates are ranked,
   // the next pop is known, and its block is loaded while the beam is updated.
   BV nxt;
   uint32_t nxt_id = kEmpty;
+  int since = 0, nevals = 0;  // learned stop: expansions since NN changed, evaluations so far
 
   for (;;) {
     // pop the first unchecked entry (the beam is kept sorted by (key, id)); the
@@ -468,7 +545,8 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const uint32_t nb = (uint32_t)b.nb;
     bool valid = (lane % LPN == 0) && b.nb >= 0;
     if (valid) valid = !visited_contains<GV>(vis, nb);
-    appended += __popcll(ballot(valid));
+    const int app = uni((int)__popcll(ballot(valid)));
+    appended += app;
     if (size == ef && valid) valid = kv_less(est, nb, tail_k, tail_i);
     const uint64_t V = ballot(valid);
     const int nv = uni((int)__popcll(V));
@@ -505,9 +583,13 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         }
       }
     }
+    float bfk = o2k;  // estimate of the next entry to pop after this expansion
     {
       uint32_t nx = o2i;
-      if (nv > 0 && (o2i == kEmpty || kv_less(bk, bi, o2k, o2i))) nx = bi;
+      if (nv > 0 && (o2i == kEmpty || kv_less(bk, bi, o2k, o2i))) {
+        nx = bi;
+        bfk = bk;
+      }
       if (nx != kEmpty && !visited_contains<GV>(vis, nx)) {
         nxt.load(a.blocks + (int64_t)nx * a.block_bytes, lane);
         nxt_id = nx;
@@ -515,7 +597,9 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     }
 
     // implicit re-ranking: NN keeps the k smallest (distance, id) seen
+    ++since;
     if (nnc < k || kv_less(dp, p, nn_wk, nn_wi)) {
+      since = 0;
       int pos = 0;
       for (int base = 0; base < nnc; base += 64) {
         const int i = base + lane;
@@ -551,8 +635,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       }
     }
 
-    if (nv == 0) continue;
-
+    if (nv > 0) {
     // Merge (truncated to ef): old entry i moves to i + cnt_i, cnt_i = number of
     // candidates strictly before it; the candidate of rank r lands at r + lb,
     // lb = number of old entries <= it (an old entry precedes an equal new one).
@@ -596,6 +679,29 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const int first = uni((int)rdlane((uint32_t)npos, t0));
     if (first < cursor) cursor = first;
     size = (size + nv < ef) ? size + nv : ef;
+    }
+
+    if constexpr (LS) {
+      if (expansions >= a.ls_t_min && (expansions - a.ls_t_min) % a.ls_t_every == 0) {
+        StopFeatures F;
+        const float nn1 = uni(nkey[0]), nnk = uni(nkey[nnc - 1]);
+        F.compute(expansions, pops, nnc, k, since, de, nn1, nnk, bfk, size, ef, dp, app, R);
+        const float out = a.ls_w ? stop_mlp(a.ls_w, F, lane) : __builtin_nanf("");
+        if (nevals < a.tr_max) {
+          const int64_t slot = q * a.tr_max + nevals;
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (lane == i) a.tr_feat[slot * 16 + i] = F.f[i];
+          for (int i = lane; i < k; i += 64) a.tr_nn[slot * k + i] = i < nnc ? (int32_t)nid[i] : -1;
+          if (lane == 0) a.tr_out[slot] = out;
+        }
+        ++nevals;
+        if (a.ls_w && out > a.ls_theta) break;
+      }
+    }
+  }
+  if constexpr (LS) {
+    if (a.tr_max > 0 && lane == 0) a.tr_count[q] = nevals < a.tr_max ? nevals : a.tr_max;
   }
 
   // answer: NN ascending by (distance, id), padded with (-1, inf)
@@ -616,7 +722,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // GV = false: main pass over all queries with the LDS visited hash.
 // GV = true : overflow pass over the queries the main pass handed over, with
 //             a global bitset per wavefront.
-template <int D, int R, bool GV>
+template <int D, int R, bool GV, bool LS>
 __global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
@@ -634,7 +740,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
     qi = __shfl(qi, 0, 64);
     if (qi >= limit) break;
     const int64_t q = GV ? (int64_t)a.overflow_list[qi] : (int64_t)qi;
-    search_one<D, R, GV>(a, q, lds, L, gbits);
+    search_one<D, R, GV, LS>(a, q, lds, L, gbits);
   }
 }
 
@@ -695,9 +801,9 @@ hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, con
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV>
+template <int D, int R, bool GV, bool LS>
 static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t lds, hipStream_t st) {
-  auto kern = search_kernel<D, R, GV>;
+  auto kern = search_kernel<D, R, GV, LS>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -707,30 +813,39 @@ static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV>
+template <int D, int R, bool GV, bool LS>
 static int occupancy_t(int wpb, size_t lds) {
   int nb = 0;
-  auto kern = search_kernel<D, R, GV>;
+  auto kern = search_kernel<D, R, GV, LS>;
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 64 * wpb, lds) != hipSuccess) return 0;
   return nb;
 }
 
-hipError_t launch_search(int D, int R, bool overflow_pass, const SearchArgs& a, int grid, int wpb, size_t lds,
-                         hipStream_t st) {
-#define QG_CASE(d, r)                                                                            \
-  if (D == d && R == r)                                                                          \
-    return overflow_pass ? launch_search_t<d, r, true>(a, grid, wpb, lds, st)                    \
-                         : launch_search_t<d, r, false>(a, grid, wpb, lds, st);
+hipError_t launch_search(int D, int R, bool overflow_pass, bool learned_stop, const SearchArgs& a, int grid, int wpb,
+                         size_t lds, hipStream_t st) {
+#define QG_CASE(d, r)                                                                                  \
+  if (D == d && R == r) {                                                                              \
+    if (learned_stop)                                                                                  \
+      return overflow_pass ? launch_search_t<d, r, true, true>(a, grid, wpb, lds, st)                  \
+                           : launch_search_t<d, r, false, true>(a, grid, wpb, lds, st);                \
+    return overflow_pass ? launch_search_t<d, r, true, false>(a, grid, wpb, lds, st)                   \
+                         : launch_search_t<d, r, false, false>(a, grid, wpb, lds, st);                 \
+  }
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
   return hipErrorInvalidValue;
 }
 
-int search_occupancy(int D, int R, bool overflow_pass, int wpb, size_t lds) {
-#define QG_CASE(d, r) \
-  if (D == d && R == r) return overflow_pass ? occupancy_t<d, r, true>(wpb, lds) : occupancy_t<d, r, false>(wpb, lds);
+int search_occupancy(int D, int R, bool overflow_pass, bool learned_stop, int wpb, size_t lds) {
+#define QG_CASE(d, r)                                                                                   \
+  if (D == d && R == r) {                                                                               \
+    if (learned_stop)                                                                                   \
+      return overflow_pass ? occupancy_t<d, r, true, true>(wpb, lds) : occupancy_t<d, r, false, true>(wpb, lds); \
+    return overflow_pass ? occupancy_t<d, r, true, false>(wpb, lds) : occupancy_t<d, r, false, false>(wpb, lds);  \
+  }
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
   return 0;

@@ -20,10 +20,18 @@ QG_SEARCH_NO_ME = 1
 QG_SEARCH_SMALL_HASH = 2
 QG_MAX_EF = 2048
 QG_MAX_K = 1024
+QG_STOP_MLP_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 
-EXPORTS = ("qg_load_index", "qg_build_index", "qg_save_index", "qg_search", "qg_search_ex", "qg_rotate",
+EXPORTS = ("qg_load_index", "qg_build_index", "qg_save_index", "qg_search", "qg_search_ex", "qg_search_stop",
+           "qg_rotate",
            "qg_estimate", "qg_copy_blocks", "qg_set_stream", "qg_index_info", "qg_timing", "qg_timing_read",
            "qg_free_index", "qg_last_error")
+
+
+class StopParams(ctypes.Structure):
+    _fields_ = [("mlp", ctypes.c_void_p), ("theta", ctypes.c_float), ("t_min", ctypes.c_int32),
+                ("t_every", ctypes.c_int32), ("trace_max", ctypes.c_int32), ("trace_features", ctypes.c_void_p),
+                ("trace_nn", ctypes.c_void_p), ("trace_out", ctypes.c_void_p), ("trace_count", ctypes.c_void_p)]
 
 
 class QGError(RuntimeError):
@@ -44,6 +52,7 @@ def _load():
         "qg_save_index": ([P, ctypes.c_char_p], c_int),
         "qg_search": ([P, P, i64, i32, i32, P, P], c_int),
         "qg_search_ex": ([P, P, i64, i32, i32, i32, P, P, P], c_int),
+        "qg_search_stop": ([P, P, i64, i32, i32, i32, ctypes.POINTER(StopParams), P, P, P], c_int),
         "qg_rotate": ([P, P, i64, P], c_int),
         "qg_estimate": ([P, P, P, i64, P, P, P], c_int),
         "qg_copy_blocks": ([P, i64, i64, P], c_int),
@@ -119,6 +128,25 @@ class Index:
         qg_search_ex(self, queries, nq, k, ef, flags, ids, dists, st)
         return (ids, dists, st) if stats else (ids, dists)
 
+    def search_stop(self, queries: torch.Tensor, k: int, ef: int, mlp: torch.Tensor | None, theta: float = 0.0,
+                    t_min: int = 8, t_every: int = 4, trace_max: int = 0, flags: int = 0, stats: bool = False):
+        """Search with the learned stop (mlp: uint16/int16 bf16 bits on the device, or None for
+        trace only).  Returns (ids, dists, stats or None, trace or None); trace =
+        (features [nq,T,16], nn [nq,T,k], out [nq,T], count [nq])."""
+        nq = queries.shape[0]
+        dev = queries.device
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=dev) if stats else None
+        tr = None
+        if trace_max > 0:
+            tr = (torch.zeros((nq, trace_max, 16), dtype=torch.float32, device=dev),
+                  torch.zeros((nq, trace_max, k), dtype=torch.int32, device=dev),
+                  torch.zeros((nq, trace_max), dtype=torch.float32, device=dev),
+                  torch.zeros((nq,), dtype=torch.int32, device=dev))
+        qg_search_stop(self, queries, nq, k, ef, flags, mlp, theta, t_min, t_every, trace_max, tr, ids, dists, st)
+        return ids, dists, st, tr
+
     def rotate(self, x: torch.Tensor) -> torch.Tensor:
         out = torch.empty_like(x)
         qg_rotate(self, x, x.shape[0], out)
@@ -193,6 +221,31 @@ def qg_search_ex(idx: Index, queries, nq: int, k: int, ef: int, flags: int, out_
     st = _dev(out_stats, torch.int32, "out_stats") if out_stats is not None else None
     _check(_lib.qg_search_ex(idx.handle, _dev(queries, torch.float32, "queries"), nq, k, ef, flags,
                              _dev(out_ids, torch.int32, "out_ids"), _dev(out_dists, torch.float32, "out_dists"), st))
+
+
+def qg_search_stop(idx: Index, queries, nq: int, k: int, ef: int, flags: int, mlp, theta: float, t_min: int,
+                   t_every: int, trace_max: int, trace, out_ids, out_dists, out_stats=None):
+    if queries.shape != (nq, idx.d) or out_ids.shape != (nq, k) or out_dists.shape != (nq, k):
+        raise ValueError("shape mismatch")
+    sp = StopParams()
+    if mlp is not None:
+        if mlp.numel() != QG_STOP_MLP_PARAMS or mlp.element_size() != 2:
+            raise ValueError("MLP parameters must be QG_STOP_MLP_PARAMS 16-bit values")
+        sp.mlp = _dev(mlp, mlp.dtype, "mlp")
+    sp.theta, sp.t_min, sp.t_every, sp.trace_max = float(theta), int(t_min), int(t_every), int(trace_max)
+    if trace_max > 0:
+        f, n, o, c = trace
+        if f.shape != (nq, trace_max, 16) or n.shape != (nq, trace_max, k) or o.shape != (nq, trace_max) \
+                or c.shape != (nq,):
+            raise ValueError("trace shape mismatch")
+        sp.trace_features = _dev(f, torch.float32, "trace_features")
+        sp.trace_nn = _dev(n, torch.int32, "trace_nn")
+        sp.trace_out = _dev(o, torch.float32, "trace_out")
+        sp.trace_count = _dev(c, torch.int32, "trace_count")
+    st = _dev(out_stats, torch.int32, "out_stats") if out_stats is not None else None
+    _check(_lib.qg_search_stop(idx.handle, _dev(queries, torch.float32, "queries"), nq, k, ef, flags,
+                               ctypes.byref(sp), _dev(out_ids, torch.int32, "out_ids"),
+                               _dev(out_dists, torch.float32, "out_dists"), st))
 
 
 def qg_search(idx: Index, queries, nq: int, k: int, ef: int, out_ids, out_dists) -> None:

@@ -44,7 +44,7 @@ CONFIGS = {
 
 
 def seed(cfg: int, what: str) -> int:
-    return 1000 * cfg + {"data": 1, "queries": 2, "rotation": 3, "graph": 4, "fill": 5, "long": 6}[what]
+    return 1000 * cfg + {"data": 1, "queries": 2, "rotation": 3, "graph": 4, "fill": 5, "long": 6, "train": 7}[what]
 
 
 def _rng(s: int) -> np.random.Generator:
@@ -58,13 +58,15 @@ def _normalize(x: np.ndarray) -> np.ndarray:
 
 
 def gen_data(cfg: int, n: int | None = None, nq: int | None = None, D: int | None = None, **kw):
-    """(X[n, D], Q[nq, D]) float32 for config ``cfg``; n/nq/D override the sizes."""
+    """(X[n, D], Q[nq, D]) float32 for config ``cfg``; n/nq/D override the sizes.
+    ``qseed`` draws the queries from another seed (e.g. training queries for the
+    learned stop); the data distribution does not depend on it."""
     c = CONFIGS[cfg]
     n = c.N if n is None else n
     nq = c.nq if nq is None else nq
     D = c.D if D is None else D
     g = _rng(seed(cfg, "data"))
-    gq = _rng(seed(cfg, "queries"))
+    gq = _rng(kw.get("qseed", seed(cfg, "queries")))
     if cfg == 1:
         mu = g.standard_normal((16, D))
         X = mu[g.integers(0, 16, n)] + 0.3 * g.standard_normal((n, D))

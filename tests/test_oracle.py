@@ -447,3 +447,65 @@ def test_space_lower_bound_and_file(tmp_path):
     for byte in raw[4096:]:
         h = ((h ^ byte) * 0x100000001b3) & (2 ** 64 - 1)
     assert cks == h
+
+
+# ------------------------------------------------------------ learned stop
+
+def _random_mlp(seed, scale=0.4):
+    rng = np.random.default_rng(seed)
+    w = (rng.standard_normal(oracle.LS_PARAMS) * scale).astype(np.float32)
+    return (w.view(np.uint32) >> 16).astype(np.uint16)  # truncate to bf16 bits
+
+
+def _bf16(u16):
+    return (u16.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def test_ls_mlp_matches_fp64_forward():
+    """The stop MLP is 16-64-64-1 with ReLU and the documented parameter
+    layout: the oracle's fp32 evaluation matches an independent fp64 forward pass."""
+    w = _random_mlp(3)
+    p = _bf16(w)
+    W1, b1 = p[:1024].reshape(64, 16), p[1024:1088]
+    W2, b2 = p[1088:1088 + 4096].reshape(64, 64), p[5184:5248]
+    W3, b3 = p[5248:5312], p[5312]
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        f = rng.uniform(0, 4, 16).astype(np.float32)
+        h1 = np.maximum(W1 @ f + b1, 0)
+        h2 = np.maximum(W2 @ h1 + b2, 0)
+        ref = W3 @ h2 + b3
+        assert abs(oracle.ls_mlp(w, f) - ref) <= 1e-4 * (1 + abs(ref))
+
+
+def test_ls_trace_features_and_limits():
+    """Trace features follow their definitions (expansion count, NN fill and
+    NN distances relative to the entry, recomputed here from the traced ids),
+    theta = +inf never stops and theta = -inf stops at the first evaluation."""
+    X, M, G, e = _tiny_index(N=500, D=64, R=16)
+    blocks = oracle.encode(X, G, M)
+    Q = np.random.default_rng(21).standard_normal((8, 64)).astype(np.float32)
+    k, ef, t_min, t_every = 5, 32, 3, 2
+    plain = oracle.search(blocks, 64, 16, e, M, Q, k, ef, with_stats=True)
+    ids, d, st, (tf, tn, to, tc) = oracle.search_ls(blocks, 64, 16, e, M, Q, k, ef, t_min=t_min, t_every=t_every,
+                                                    max_evals=64)
+    assert (ids == plain[0]).all() and (st == plain[2]).all()
+    de = [oracle.exact_dist(q, X[e]) for q in Q]
+    for i in range(Q.shape[0]):
+        assert tc[i] == min(64, (st[i, 0] - t_min) // t_every + 1)
+        for j in range(tc[i]):
+            f = tf[i, j]
+            E = t_min + j * t_every
+            assert f[0] == np.float32(E) / 64 and f[15] == 1.0
+            nn = tn[i, j][tn[i, j] >= 0]
+            assert f[2] == np.float32(len(nn)) / np.float32(k)
+            dn = [oracle.exact_dist(Q[i], X[v]) for v in nn]
+            assert dn == sorted(dn)
+            assert f[4] == min(np.float32(8), np.float32(dn[0]) / np.float32(de[i]))
+            assert f[5] == min(np.float32(8), np.float32(dn[-1]) / np.float32(de[i]))
+            assert np.isnan(to[i, j])
+    w = _random_mlp(5)
+    never = oracle.search_ls(blocks, 64, 16, e, M, Q, k, ef, w=w, theta=np.inf, t_min=t_min, t_every=t_every)
+    assert (never[0] == plain[0]).all() and (never[2] == plain[2]).all()
+    first = oracle.search_ls(blocks, 64, 16, e, M, Q, k, ef, w=w, theta=-np.inf, t_min=t_min, t_every=t_every)
+    assert (first[2][:, 0] == np.minimum(t_min, plain[2][:, 0])).all()
