@@ -40,10 +40,22 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
 __device__ __forceinline__ float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
 
-// (key, id) lexicographic order.
+// (key, id) lexicographic order, without branches.
 __device__ __forceinline__ bool kv_less(float ka, uint32_t ia, float kb, uint32_t ib) {
-  return ka < kb || (ka == kb && ia < ib);
+  return (ka < kb) | ((ka == kb) & (ia < ib));
 }
+
+// (key, id) packed into one unsigned 64-bit integer whose order is the
+// lexicographic (key, id) order of the floats: -0 is first mapped to +0 (the
+// two compare equal), then the usual sign flip makes the bits sortable.
+__device__ __forceinline__ uint32_t sortable(float x) {
+  const uint32_t u = __float_as_uint(x + 0.0f);
+  return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+}
+__device__ __forceinline__ float unsortable(uint32_t s) {
+  return __uint_as_float((s & 0x80000000u) ? (s ^ 0x80000000u) : ~s);
+}
+__device__ __forceinline__ uint64_t pack_kv(float key, uint32_t id) { return ((uint64_t)sortable(key) << 32) | id; }
 
 __device__ __forceinline__ float wave_max(float v) {
   for (int s = 32; s >= 1; s >>= 1) v = fmaxf(v, __shfl_xor(v, s, 64));
@@ -430,15 +442,22 @@ __device__ __forceinline__ float stop_mlp(const uint16_t* __restrict__ w, const 
   return uni(butterfly_f(pr) + bf16at(w, kLsB3));
 }
 
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
+  return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
+}
+
 template <int D, int R, bool GV, bool LS>
 __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L, uint32_t* gbits) {
   using BV = BlockView<D, R>;
   constexpr int DPL = BV::DPL;
   constexpr int LPN = BV::LPN;
+  constexpr uint64_t kNone = ~0ull;  // sorts after every real entry
   const int lane = lane_id();
   const int ef = a.ef, k = a.k;
   int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
-  uint2* beam = reinterpret_cast<uint2*>(lds + L.beam);  // sorted (key bits, id | checked)
+  // beam entries: sortable(key) << 32 | id | checked, kept in ascending order
+  uint64_t* beam = reinterpret_cast<uint64_t*>(lds + L.beam);
+  uint32_t* beam_lo = reinterpret_cast<uint32_t*>(lds + L.beam);  // low words (id | checked)
   float* nkey = reinterpret_cast<float*>(lds + L.nkey);
   uint32_t* nid = reinterpret_cast<uint32_t*>(lds + L.nid);
 
@@ -472,14 +491,13 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     BV e;
     e.load(a.blocks + (int64_t)a.entry * a.block_bytes, lane);
     de = uni(exact_dist<DPL>(qv, e.x));
-    beam[0] = make_uint2(__float_as_uint(de), (uint32_t)a.entry);
-    wave_sync();
   }
+  uint64_t tail = pack_kv(de, (uint32_t)a.entry);  // beam[ef - 1] whenever the beam is full
+  beam[0] = tail;
+  wave_sync();
   int size = 1, cursor = 0, nnc = 0;
   float nn_wk = 0.0f;  // worst (distance, id) of NN once it holds k entries
   uint32_t nn_wi = 0;
-  float tail_k = de;  // beam[ef - 1] whenever the beam is full (from the start when ef = 1)
-  uint32_t tail_i = (uint32_t)a.entry;
   int expansions = 0, pops = 0, appended = 0;
   // Next-vertex prefetch (Sec. 3.1.4): once the new candidates are ranked,
   // the next pop is known, and its block is loaded while the beam is updated.
@@ -488,27 +506,23 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   int since = 0, nevals = 0;  // learned stop: expansions since NN changed, evaluations so far
 
   for (;;) {
-    // pop the first unchecked entry (the beam is kept sorted by (key, id)); the
-    // same chunk read gives the next unchecked entry after it
+    // pop the first unchecked entry; the same chunk read gives the next
+    // unchecked entry after it (o2)
     int c = -1;
     uint32_t p = 0;
-    float o2k = __builtin_inff();
-    uint32_t o2i = kEmpty;
+    uint64_t o2 = kNone;
     bool o2_known = false;
     while (cursor < size) {
       const int i = cursor + lane;
-      uint2 e = make_uint2(0u, kChecked);
-      if (i < size) e = beam[i];
-      const uint64_t m = ballot(!(e.y & kChecked));
+      const uint64_t e = (i < size) ? beam[i] : (uint64_t)kChecked;
+      const uint64_t m = ballot(!((uint32_t)e & kChecked));
       if (m) {
         const int f = first_lane(m);
         c = cursor + f;
-        p = rdlane(e.y, f);
+        p = rdlane((uint32_t)e, f);
         const uint64_t m2 = m & (m - 1);
         if (m2) {
-          const int f2 = first_lane(m2);
-          o2k = rdlane(__uint_as_float(e.x), f2);
-          o2i = rdlane(e.y, f2);
+          o2 = rdlane64(e, first_lane(m2));
           o2_known = true;
         } else {
           o2_known = cursor + 64 >= size;  // nothing unchecked after c
@@ -518,7 +532,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       cursor += 64;
     }
     if (c < 0) break;
-    beam[c].y = p | kChecked;  // every lane stores the same word
+    beam_lo[2 * c] = p | kChecked;  // every lane stores the same word
     cursor = c + 1;
     ++pops;
     if (visited_insert<GV>(vis, p, lane)) continue;  // a second estimate of a visited vertex
@@ -543,54 +557,44 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const int S = b.fastscan(lut, lane);
     const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
     const uint32_t nb = (uint32_t)b.nb;
+    const uint64_t cand = pack_kv(est, nb);
     bool valid = (lane % LPN == 0) && b.nb >= 0;
     if (valid) valid = !visited_contains<GV>(vis, nb);
     const int app = uni((int)__popcll(ballot(valid)));
     appended += app;
-    if (size == ef && valid) valid = kv_less(est, nb, tail_k, tail_i);
+    if (size == ef) valid = valid && cand < tail;  // would fall past the cut anyway
     const uint64_t V = ballot(valid);
     const int nv = uni((int)__popcll(V));
 
-    // rank the candidates by (estimate, id): candidate t is broadcast from its
-    // lane through a scalar register, no LDS round trip
-    int sidx = 0;
-    for (uint64_t mm = V; mm; mm &= mm - 1) {
-      const int t = first_lane(mm);
-      sidx += kv_less(rdlane(est, t), rdlane(nb, t), est, nb) ? 1 : 0;
-    }
-    int t0 = -1;  // lane of the best candidate
-    float bk = __builtin_inff();
-    uint32_t bi = kEmpty;
+    // best candidate, then the next pop: the smaller of it and the first
+    // unchecked old entry; prefetch its block unless it is already visited
+    uint64_t best = kNone;
     if (nv > 0) {
-      t0 = first_lane(ballot(valid && sidx == 0));
-      bk = rdlane(est, t0);
-      bi = rdlane(nb, t0);
+      uint64_t mine = valid ? cand : kNone;
+#pragma unroll
+      for (int sft = 32; sft >= 1; sft >>= 1) {
+        const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(mine >> 32), sft, 64) << 32) |
+                           (uint32_t)__shfl_xor((int)(uint32_t)mine, sft, 64);
+        mine = o < mine ? o : mine;
+      }
+      best = ((uint64_t)uni((uint32_t)(mine >> 32)) << 32) | uni((uint32_t)mine);
     }
-
-    // the next pop: the smaller of the best candidate and the first unchecked
-    // old entry; prefetch its block unless it is already visited
     if (!o2_known) {
       for (int base = cursor; base < size; base += 64) {
         const int i = base + lane;
-        uint2 e = make_uint2(0u, kChecked);
-        if (i < size) e = beam[i];
-        const uint64_t m = ballot(!(e.y & kChecked));
+        const uint64_t e = (i < size) ? beam[i] : (uint64_t)kChecked;
+        const uint64_t m = ballot(!((uint32_t)e & kChecked));
         if (m) {
-          const int f = first_lane(m);
-          o2k = rdlane(__uint_as_float(e.x), f);
-          o2i = rdlane(e.y, f);
+          o2 = rdlane64(e, first_lane(m));
           break;
         }
       }
     }
-    float bfk = o2k;  // estimate of the next entry to pop after this expansion
-    {
-      uint32_t nx = o2i;
-      if (nv > 0 && (o2i == kEmpty || kv_less(bk, bi, o2k, o2i))) {
-        nx = bi;
-        bfk = bk;
-      }
-      if (nx != kEmpty && !visited_contains<GV>(vis, nx)) {
+    const uint64_t nxt_kv = best < o2 ? best : o2;  // the entry popped next
+    const float bfk = nxt_kv == kNone ? __builtin_inff() : unsortable((uint32_t)(nxt_kv >> 32));
+    if (nxt_kv != kNone) {
+      const uint32_t nx = (uint32_t)nxt_kv & kIdMask;
+      if (!visited_contains<GV>(vis, nx)) {
         nxt.load(a.blocks + (int64_t)nx * a.block_bytes, lane);
         nxt_id = nx;
       }
@@ -636,49 +640,65 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     }
 
     if (nv > 0) {
-    // Merge (truncated to ef): old entry i moves to i + cnt_i, cnt_i = number of
-    // candidates strictly before it; the candidate of rank r lands at r + lb,
-    // lb = number of old entries <= it (an old entry precedes an equal new one).
-    // Chunks go top down, so no entry is overwritten before it is read.
-    int lbv = 0;  // lane t accumulates lb of the candidate held in lane t
-    for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {
-      const int i = base + lane;
-      const bool live = i < size;
-      uint2 e = make_uint2(0u, 0u);
-      if (live) e = beam[i];
-      const float ek = __uint_as_float(e.x);
-      const uint32_t ei = e.y & kIdMask;
-      int cnt = 0;
-      for (uint64_t mm = V; mm; mm &= mm - 1) {
-        const int t = first_lane(mm);
-        const bool lt = kv_less(rdlane(est, t), rdlane(nb, t), ek, ei);
-        cnt += lt ? 1 : 0;
-        const int le = __popcll(ballot(live && !lt));
-        lbv += (lane == t) ? le : 0;
+      // Merge, truncated to ef: old entry i moves to i + cnt_i (cnt_i = number of
+      // candidates strictly before it); the candidate of rank r lands at r + lb
+      // (lb = number of old entries <= it, so an old entry precedes an equal new
+      // one).  Candidates are broadcast from their lanes through scalar
+      // registers; all old entries are read before any is written.
+      int sidx = 0;  // rank of this lane's candidate
+      int lbv = 0;   // lb of this lane's candidate
+      if (size <= 128) {
+        const bool live0 = lane < size, live1 = lane + 64 < size;
+        const uint64_t e0 = live0 ? beam[lane] : 0ull, e1 = live1 ? beam[lane + 64] : 0ull;
+        const uint64_t k0 = e0 & ~(uint64_t)kChecked, k1 = e1 & ~(uint64_t)kChecked;
+        const uint64_t L0 = ballot(live0), L1 = ballot(live1);
+        int c0 = 0, c1 = 0;
+        for (uint64_t mm = V; mm; mm &= mm - 1) {
+          const int t = first_lane(mm);
+          const uint64_t ct = rdlane64(cand, t);
+          const bool lt0 = ct < k0, lt1 = ct < k1;
+          c0 += lt0;
+          c1 += lt1;
+          sidx += ct < cand;
+          const int le = __popcll(L0 & ~ballot(lt0)) + __popcll(L1 & ~ballot(lt1));
+          lbv = (lane == t) ? le : lbv;
+        }
+        const int np0 = lane + c0, np1 = lane + 64 + c1;
+        const uint64_t t0m = ballot(live0 && np0 == ef - 1), t1m = ballot(live1 && np1 == ef - 1);
+        if (t0m) tail = rdlane64(k0, first_lane(t0m));
+        if (t1m) tail = rdlane64(k1, first_lane(t1m));
+        if (live0 && np0 < ef) beam[np0] = e0;
+        if (live1 && np1 < ef) beam[np1] = e1;
+      } else {
+        for (uint64_t mm = V; mm; mm &= mm - 1) sidx += rdlane64(cand, first_lane(mm)) < cand;
+        for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {  // top down
+          const int i = base + lane;
+          const bool live = i < size;
+          const uint64_t e = live ? beam[i] : 0ull;
+          const uint64_t ke = e & ~(uint64_t)kChecked;
+          const uint64_t Lm = ballot(live);
+          int cnt = 0;
+          for (uint64_t mm = V; mm; mm &= mm - 1) {
+            const int t = first_lane(mm);
+            const bool lt = rdlane64(cand, t) < ke;
+            cnt += lt;
+            const int le = __popcll(Lm & ~ballot(lt));
+            lbv += (lane == t) ? le : 0;
+          }
+          const int np = i + cnt;
+          const uint64_t tm = ballot(live && np == ef - 1);
+          if (tm) tail = rdlane64(ke, first_lane(tm));
+          if (live && np < ef) beam[np] = e;
+        }
       }
-      const int np = i + cnt;
-      const uint64_t tm = ballot(live && np == ef - 1);
-      if (tm) {
-        const int f = first_lane(tm);
-        tail_k = rdlane(ek, f);
-        tail_i = rdlane(ei, f);
-      }
-      if (live && np < ef) beam[np] = e;
-    }
-    const int npos = sidx + lbv;
-    if (valid && npos < ef) beam[npos] = make_uint2(__float_as_uint(est), nb);
-    {
+      const int npos = sidx + lbv;
+      if (valid && npos < ef) beam[npos] = cand;
       const uint64_t tm = ballot(valid && npos == ef - 1);
-      if (tm) {
-        const int f = first_lane(tm);
-        tail_k = rdlane(est, f);
-        tail_i = rdlane(nb, f);
-      }
-    }
-    wave_sync();
-    const int first = uni((int)rdlane((uint32_t)npos, t0));
-    if (first < cursor) cursor = first;
-    size = (size + nv < ef) ? size + nv : ef;
+      if (tm) tail = rdlane64(cand, first_lane(tm));
+      wave_sync();
+      const int first = uni(__shfl(npos, first_lane(ballot(valid && sidx == 0)), 64));
+      if (first < cursor) cursor = first;
+      size = (size + nv < ef) ? size + nv : ef;
     }
 
     if constexpr (LS) {
