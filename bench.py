@@ -41,12 +41,14 @@ def main():
     ap.add_argument("--nq", type=int, default=10_000)
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--cpu-sample", type=int, default=10_000, help="queries searched by the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="the oracle repeats the query sample until about this much wall time has passed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--save-index", default="")
     ap.add_argument("--ef", type=int, default=0, help="skip the sweep and time this beam size")
     ap.add_argument("--load-index", default="", help="search a saved index (no recall: ground truth is not rebuilt)")
     ap.add_argument("--no-learned-stop", action="store_true", help="time only the fixed-ef search")
-    ap.add_argument("--ls-ef", type=int, default=0, help="beam size for the learned stop (default: 2x the fixed ef)")
+    ap.add_argument("--ls-ef", type=int, default=0, help="beam size for the learned stop (default: the fixed ef)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -179,7 +181,7 @@ def main():
         _, Qtr = synth.gen_data(2, n=1, nq=20_000, qseed=synth.seed(2, "train"))
         gt_tr, _ = synth.ground_truth(X, Qtr, k, device=dev)
         Qtr_d, gt_tr_d = torch.from_numpy(Qtr).to(dev), torch.from_numpy(gt_tr).to(dev)
-        ls_ef = args.ls_ef or 2 * ef
+        ls_ef = args.ls_ef or ef
         t_min, t_every = 8, 4
         with torch.cuda.stream(stream):
             feat, lab = learned_stop.collect(idx, Qtr_d[:16_000].contiguous(), gt_tr_d[:16_000], k, ls_ef, t_min,
@@ -232,6 +234,51 @@ def main():
     except (OSError, ValueError, KeyError):
         pass
 
+    # streaming-read bandwidth of this device (a plain reduction over 2 GiB), the
+    # practical ceiling next to the vendor peak
+    buf = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        buf.sum()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        buf.sum()
+    ev1.record()
+    torch.cuda.synchronize()
+    read_bw = 10 * buf.numel() * 4 / (ev0.elapsed_time(ev1) / 1e3)
+    del buf
+    roofline["measured_read_gbps"] = round(read_bw / 1e9, 1)
+    roofline["frac_of_measured_read"] = round(roofline["achieved"] * 1e9 / read_bw, 4)
+    log(f"[bench] streaming read {read_bw / 1e9:.0f} GB/s")
+
+    # end to end over PCIe: queries from pinned host memory, results back to the host
+    Qh = torch.from_numpy(Q).pin_memory()
+    ids_h = torch.empty((args.nq, k), dtype=torch.int32).pin_memory()
+    d_h = torch.empty((args.nq, k), dtype=torch.float32).pin_memory()
+    use_ls = roofline["kernel"].endswith("learned stop")
+    e2e_ef = ls_res["ef"] if use_ls else ef
+
+    def e2e():
+        with torch.cuda.stream(stream):
+            Qx = Qh.to(dev, non_blocking=True)
+            if use_ls:
+                i_, d_, _, _ = idx.search_stop(Qx, k, e2e_ef, bits, theta=ls_res["theta"], t_min=ls_res["t_min"],
+                                               t_every=ls_res["t_every"])
+            else:
+                i_, d_ = idx.search(Qx, k, e2e_ef)
+            ids_h.copy_(i_, non_blocking=True)
+            d_h.copy_(d_, non_blocking=True)
+
+    for _ in range(args.warmup):
+        e2e()
+    stream.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        e2e()
+    stream.synchronize()
+    e2e_qps = args.nq * args.steps / (time.perf_counter() - t1)
+    log(f"[bench] end to end with PCIe copies: {e2e_qps:,.0f} q/s")
+
     cpu = None
     if not args.no_cpu and X is not None:
         sys.path.insert(0, os.path.join(ROOT, "oracle"))
@@ -241,16 +288,37 @@ def main():
         log(f"[bench] oracle encode in {time.time() - t0:.1f}s")
         ns = min(args.cpu_sample, args.nq)
         threads = oracle.max_threads()
-        t0 = time.perf_counter()
-        oids, odists = oracle.search(blocks, D, R, entry, M, Q[:ns], k, ef)
-        dt = time.perf_counter() - t0
+        # the sample is searched again until about --cpu-seconds have passed
+        reps, dt = 0, 0.0
+        while dt < args.cpu_seconds and reps < 1000:
+            t0 = time.perf_counter()
+            oids, odists = oracle.search(blocks, D, R, entry, M, Q[:ns], k, ef, nthreads=threads)
+            dt += time.perf_counter() - t0
+            reps += 1
         gids = run(ef)[0].cpu().numpy()[:ns]
         same = int((oids == gids).all(axis=1).sum())
-        cpu = {"value": round(ns / dt, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {ns} of the {args.nq} queries at ef={ef}, same index (oracle-encoded from the "
-                         f"same inputs), OpenMP over queries", "seconds": round(dt, 2),
-               "ids_identical_to_gpu": f"{same}/{ns}"}
-        log(f"[bench] oracle {ns} queries in {dt:.2f}s on {threads} threads; ids identical {same}/{ns}")
+        n1 = min(ns, 2000)
+        reps1, dt1 = 0, 0.0
+        while dt1 < args.cpu_seconds / 4 and reps1 < 1000:
+            t0 = time.perf_counter()
+            oracle.search(blocks, D, R, entry, M, Q[:n1], k, ef, nthreads=1)
+            dt1 += time.perf_counter() - t0
+            reps1 += 1
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        cpu = {"value": round(reps * ns / dt, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {ns} of the {args.nq} queries at ef={ef}, searched {reps} times, same index "
+                         f"(oracle-encoded from the same inputs), OpenMP over queries",
+               "seconds": round(dt, 2), "ids_identical_to_gpu": f"{same}/{ns}",
+               "one_thread_qps": round(reps1 * n1 / dt1, 1),
+               "one_thread_sample": f"first {n1} queries, searched {reps1} times",
+               "host_cpu": model, "host_logical_cpus": os.cpu_count()}
+        log(f"[bench] oracle {reps} x {ns} queries in {dt:.2f}s on {threads} threads "
+            f"({cpu['value']:,.0f} q/s; 1 thread {cpu['one_thread_qps']:,.0f} q/s); ids identical {same}/{ns}")
 
     out = {
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -264,6 +332,7 @@ def main():
                    "graph": "k-NN + random long links (input generator)"},
         "fixed_ef": fixed,
         "learned_stop": ls_res,
+        "end_to_end_qps_with_pcie": round(e2e_qps, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,

@@ -424,8 +424,9 @@ int qg_search_stop(const qg_index* cidx, const float* queries, int64_t nq, int32
   a.overflow_list = idx->overflow;
   a.fb_bits = idx->fb_bits;
   a.fb_words = idx->fb_words;
-  const bool ls = stop != nullptr;
-  if (ls) {
+  // ls_mode 1: stop only, MLP in LDS; 2: trace (and the MLP, if given, read from global memory)
+  const int ls = !stop ? 0 : (stop->trace_max == 0 && stop->mlp ? 1 : 2);
+  if (stop) {
     a.ls_w = stop->mlp;
     a.ls_theta = stop->theta;
     a.ls_t_min = stop->t_min;
@@ -440,10 +441,12 @@ int qg_search_stop(const qg_index* cidx, const float* queries, int64_t nq, int32
   const qgl::SearchLds L = qgl::search_lds(idx->D, idx->R, ef_cap, 1 << hbits, k_cap);
   const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
   const size_t lds_cap = 160 * 1024;
+  const size_t extra = ls == 1 ? qgk::mlp_lds_bytes() : 0;  // MLP image shared by a workgroup
   int wpb = 4;
-  while (wpb > 1 && (size_t)wpb * L.total > lds_cap) wpb >>= 1;
-  if ((size_t)L.total > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
-  int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, wpb, (size_t)wpb * L.total);
+  while (wpb > 1 && (size_t)wpb * L.total + extra > lds_cap) wpb >>= 1;
+  if ((size_t)L.total + extra > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
+  const size_t lds = (size_t)wpb * L.total + extra;
+  int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, wpb, lds);
   if (occ <= 0) occ = 1;
   int64_t want = (nq + wpb - 1) / wpb;
   int grid = (int)std::min<int64_t>(want, (int64_t)occ * 256);
@@ -453,10 +456,10 @@ int qg_search_stop(const qg_index* cidx, const float* queries, int64_t nq, int32
           "rotate queries");
   if ((rc = record(idx, 0, false))) return rc;
   if ((rc = record(idx, 1, true))) return rc;
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, a, grid, wpb, (size_t)wpb * L.total, idx->stream), "search");
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, a, grid, wpb, lds, idx->stream), "search");
   if ((rc = record(idx, 1, false))) return rc;
   // overflow pass: one wavefront per workgroup, one bitset each
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, a, idx->fb_slots, 1, (size_t)Lf.total, idx->stream),
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, a, idx->fb_slots, 1, (size_t)Lf.total + extra, idx->stream),
           "search overflow pass");
   return QG_OK;
 }

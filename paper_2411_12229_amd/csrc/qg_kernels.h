@@ -23,7 +23,7 @@ struct SearchArgs {
   int32_t* overflow_list; // [nq]
   uint32_t* fb_bits;      // overflow pass: one N-bit set per wavefront
   int64_t fb_words;       // 32-bit words per set
-  // learned stop (search kernels instantiated with LS = true)
+  // learned stop (ls_mode 1 and 2)
   const uint16_t* ls_w;   // MLP parameters (bf16 bits) or null: evaluate and trace only
   float ls_theta;
   int ls_t_min, ls_t_every;
@@ -50,9 +50,12 @@ hipError_t launch_rotate(const float* in, int64_t n, int D, const float* M, floa
                          hipStream_t st);
 hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, const int32_t* G, int R,
                          uint8_t* blocks, int64_t B, hipStream_t st);
-hipError_t launch_search(int D, int R, bool overflow_pass, bool learned_stop, const SearchArgs& a, int grid, int wpb,
+// ls_mode: 0 plain search, 1 learned stop (MLP staged in LDS, mlp_lds_bytes()
+// after the wavefront areas), 2 learned stop with trace (MLP read from global)
+hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const SearchArgs& a, int grid, int wpb,
                          size_t lds, hipStream_t st);
-int search_occupancy(int D, int R, bool overflow_pass, bool learned_stop, int wpb, size_t lds);
+int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, size_t lds);
+constexpr size_t mlp_lds_bytes() { return 2 * 64 * 16 + 8 * 64 * 16 + 3 * 128 + 16; }
 hipError_t launch_estimate(int D, int R, const EstimateArgs& a, int64_t nq, hipStream_t st);
 
 }  // namespace qgk

@@ -378,6 +378,9 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 // its inputs in ascending order from its bias; the output is the butterfly sum
 // of w3[j] * h2[j] plus the output bias.  Parameter layout: W1[64][16], b1[64],
 // W2[64][64], b2[64], W3[64], b3.
+// learned-stop modes of the search kernels
+constexpr int kLsOff = 0, kLsStop = 1, kLsTrace = 2;
+
 constexpr int kLsW1 = 0, kLsB1 = 64 * 16, kLsW2 = kLsB1 + 64, kLsB2 = kLsW2 + 64 * 64, kLsW3 = kLsB2 + 64,
               kLsB3 = kLsW3 + 64;
 
@@ -387,28 +390,34 @@ __device__ __forceinline__ float bf16at(const uint16_t* w, int i) { return __uin
 __device__ __forceinline__ float ratio(float a, float b) { return b > 0.0f ? a / b : 0.0f; }
 __device__ __forceinline__ float clamp8(float x) { return x < 0.0f ? 0.0f : (x > 8.0f ? 8.0f : x); }
 
+// The 16 features of the search state, each a quotient num / den (0 when
+// den <= 0) clamped to [0, 8].  Lane i (i < 16) forms feature i with one
+// division; the MLP reads feature i from lane i as it needs it.  The lane
+// index is made opaque here so that the compiler cannot hoist the 15 lane
+// compares out of the search loop (they would hold 30 scalar registers).
 struct StopFeatures {
-  float f[16];
+  float mine;  // feature (lane & 15) of this lane
   __device__ __forceinline__ void compute(int E, int P, int nnc, int k, int since, float de, float nn1, float nnk,
                                           float bf, int size, int ef, float dp, int app, int R) {
-    f[0] = (float)E / 64.0f;
-    f[1] = (float)P / 64.0f;
-    f[2] = (float)nnc / (float)k;
-    f[3] = (float)since / 16.0f;
-    f[4] = ratio(nn1, de);
-    f[5] = ratio(nnk, de);
-    f[6] = ratio(bf, nnk);
-    f[7] = ratio(bf, nn1);
-    f[8] = (float)size / (float)ef;
-    f[9] = ratio(dp, nnk);
-    f[10] = (float)app / (float)R;
-    f[11] = ratio(nnk - nn1, nnk);
-    f[12] = (float)ef / 256.0f;
-    f[13] = ratio(bf, de);
-    f[14] = (float)E / (float)ef;
-    f[15] = 1.0f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) f[i] = clamp8(f[i]);
+    int i = lane_id() & 15;
+    asm volatile("" : "+v"(i));
+    float n = (float)E, d = 64.0f;                                         // 0: expansions
+    n = i == 1 ? (float)P : n;                                             // 1: pops
+    n = i == 2 ? (float)nnc : n;    d = i == 2 ? (float)k : d;             // 2: NN fill
+    n = i == 3 ? (float)since : n;  d = i == 3 ? 16.0f : d;                // 3: expansions since NN changed
+    n = i == 4 ? nn1 : n;           d = i == 4 ? de : d;                   // 4: best / entry distance
+    n = i == 5 ? nnk : n;           d = i == 5 ? de : d;                   // 5: k-th / entry distance
+    n = i == 6 ? bf : n;            d = i == 6 ? nnk : d;                  // 6: next estimate / k-th distance
+    n = i == 7 ? bf : n;            d = i == 7 ? nn1 : d;                  // 7: next estimate / best distance
+    n = i == 8 ? (float)size : n;   d = i == 8 ? (float)ef : d;            // 8: beam fill
+    n = i == 9 ? dp : n;            d = i == 9 ? nnk : d;                  // 9: last exact distance / k-th
+    n = i == 10 ? (float)app : n;   d = i == 10 ? (float)R : d;            // 10: fraction of neighbours appended
+    n = i == 11 ? nnk - nn1 : n;    d = i == 11 ? nnk : d;                 // 11: relative spread of NN
+    n = i == 12 ? (float)ef : n;    d = i == 12 ? 256.0f : d;              // 12: beam size
+    n = i == 13 ? bf : n;           d = i == 13 ? de : d;                  // 13: next estimate / entry distance
+    n = i == 14 ? (float)E : n;     d = i == 14 ? (float)ef : d;           // 14: expansions / beam size
+    n = i == 15 ? 1.0f : n;         d = i == 15 ? 1.0f : d;                // 15: bias input
+    mine = clamp8(ratio(n, d));
   }
 };
 
@@ -420,14 +429,14 @@ __device__ __forceinline__ float stop_mlp(const uint16_t* __restrict__ w, const 
   float acc = bf16at(w, kLsB1 + lane);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    acc = __builtin_fmaf(bf16lo(wr[i]), F.f[2 * i], acc);
-    acc = __builtin_fmaf(bf16hi(wr[i]), F.f[2 * i + 1], acc);
+    acc = __builtin_fmaf(bf16lo(wr[i]), rdlane(F.mine, 2 * i), acc);
+    acc = __builtin_fmaf(bf16hi(wr[i]), rdlane(F.mine, 2 * i + 1), acc);
   }
   const float h1 = acc > 0.0f ? acc : 0.0f;
   // layer 2: every lane needs all 64 h1 values; they come through scalar registers
   const uint4* r2 = reinterpret_cast<const uint4*>(w + kLsW2 + lane * 64);
   acc = bf16at(w, kLsB2 + lane);
-#pragma unroll
+#pragma unroll 2
   for (int c = 0; c < 8; ++c) {
     const uint4 v = r2[c];
     const uint32_t u[4] = {v.x, v.y, v.z, v.w};
@@ -442,12 +451,63 @@ __device__ __forceinline__ float stop_mlp(const uint16_t* __restrict__ w, const 
   return uni(butterfly_f(pr) + bf16at(w, kLsB3));
 }
 
+// The stop-only kernels keep the MLP in LDS, staged once per workgroup and
+// laid out so that lane j's 16-byte chunk c of a weight row sits at chunk
+// c * 64 + j (consecutive lanes read consecutive chunks, no bank conflicts):
+// W1 as 2 x 64 chunks, W2 as 8 x 64 chunks, then b1[64], b2[64], W3[64], b3.
+constexpr int kMlpW2 = 2 * 64 * 16, kMlpB1 = kMlpW2 + 8 * 64 * 16, kMlpB2 = kMlpB1 + 128, kMlpW3 = kMlpB2 + 128,
+              kMlpB3 = kMlpW3 + 128;
+
+__device__ __forceinline__ void stage_mlp(const uint16_t* __restrict__ w, uint8_t* m) {
+  for (int t = threadIdx.x; t < 10 * 64; t += blockDim.x) {
+    const int c = t < 128 ? t >> 6 : (t - 128) >> 6, j = t & 63;
+    const uint4* src = t < 128 ? reinterpret_cast<const uint4*>(w + kLsW1 + j * 16) + c
+                               : reinterpret_cast<const uint4*>(w + kLsW2 + j * 64) + c;
+    reinterpret_cast<uint4*>(m)[t] = *src;
+  }
+  uint16_t* m16 = reinterpret_cast<uint16_t*>(m + kMlpB1);
+  for (int t = threadIdx.x; t < 64 + 129; t += blockDim.x)
+    m16[t] = t < 64 ? w[kLsB1 + t] : w[kLsB2 + (t - 64)];  // b2, W3 and b3 are contiguous
+}
+
+__device__ __forceinline__ float stop_mlp_lds(const uint8_t* m, float f, int lane) {
+  const uint4* W = reinterpret_cast<const uint4*>(m);
+  const uint16_t* m16 = reinterpret_cast<const uint16_t*>(m + kMlpB1);
+  float acc = __uint_as_float((uint32_t)m16[lane] << 16);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const uint4 v = W[c * 64 + lane];
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      acc = __builtin_fmaf(bf16lo(u[h]), rdlane(f, 8 * c + 2 * h), acc);
+      acc = __builtin_fmaf(bf16hi(u[h]), rdlane(f, 8 * c + 2 * h + 1), acc);
+    }
+  }
+  const float h1 = acc > 0.0f ? acc : 0.0f;
+  acc = __uint_as_float((uint32_t)m16[64 + lane] << 16);
+#pragma unroll 2
+  for (int c = 0; c < 8; ++c) {
+    const uint4 v = W[(2 + c) * 64 + lane];
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      acc = __builtin_fmaf(bf16lo(u[h]), rdlane(h1, 8 * c + 2 * h), acc);
+      acc = __builtin_fmaf(bf16hi(u[h]), rdlane(h1, 8 * c + 2 * h + 1), acc);
+    }
+  }
+  const float h2 = acc > 0.0f ? acc : 0.0f;
+  const float pr = __uint_as_float((uint32_t)m16[128 + lane] << 16) * h2;
+  return uni(butterfly_f(pr) + __uint_as_float((uint32_t)m16[192] << 16));
+}
+
 __device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
   return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
 }
 
-template <int D, int R, bool GV, bool LS>
-__device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L, uint32_t* gbits) {
+template <int D, int R, bool GV, int LS>
+__device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L, uint32_t* gbits,
+                           const uint8_t* mlp) {
   using BV = BlockView<D, R>;
   constexpr int DPL = BV::DPL;
   constexpr int LPN = BV::LPN;
@@ -701,26 +761,30 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       size = (size + nv < ef) ? size + nv : ef;
     }
 
-    if constexpr (LS) {
+    if constexpr (LS != kLsOff) {
       if (expansions >= a.ls_t_min && (expansions - a.ls_t_min) % a.ls_t_every == 0) {
         StopFeatures F;
         const float nn1 = uni(nkey[0]), nnk = uni(nkey[nnc - 1]);
         F.compute(expansions, pops, nnc, k, since, de, nn1, nnk, bfk, size, ef, dp, app, R);
-        const float out = a.ls_w ? stop_mlp(a.ls_w, F, lane) : __builtin_nanf("");
-        if (nevals < a.tr_max) {
-          const int64_t slot = q * a.tr_max + nevals;
-#pragma unroll
-          for (int i = 0; i < 16; ++i)
-            if (lane == i) a.tr_feat[slot * 16 + i] = F.f[i];
-          for (int i = lane; i < k; i += 64) a.tr_nn[slot * k + i] = i < nnc ? (int32_t)nid[i] : -1;
-          if (lane == 0) a.tr_out[slot] = out;
+        float out;
+        if constexpr (LS == kLsStop)
+          out = stop_mlp_lds(mlp, F.mine, lane);
+        else
+          out = a.ls_w ? stop_mlp(a.ls_w, F, lane) : __builtin_nanf("");
+        if constexpr (LS == kLsTrace) {
+          if (nevals < a.tr_max) {
+            const int64_t slot = q * a.tr_max + nevals;
+            if (lane < 16) a.tr_feat[slot * 16 + lane] = F.mine;
+            for (int i = lane; i < k; i += 64) a.tr_nn[slot * k + i] = i < nnc ? (int32_t)nid[i] : -1;
+            if (lane == 0) a.tr_out[slot] = out;
+          }
+          ++nevals;
         }
-        ++nevals;
-        if (a.ls_w && out > a.ls_theta) break;
+        if (out > a.ls_theta) break;  // false for NaN: no model, no stop
       }
     }
   }
-  if constexpr (LS) {
+  if constexpr (LS == kLsTrace) {
     if (a.tr_max > 0 && lane == 0) a.tr_count[q] = nevals < a.tr_max ? nevals : a.tr_max;
   }
 
@@ -742,13 +806,18 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // GV = false: main pass over all queries with the LDS visited hash.
 // GV = true : overflow pass over the queries the main pass handed over, with
 //             a global bitset per wavefront.
-template <int D, int R, bool GV, bool LS>
+template <int D, int R, bool GV, int LS>
 __global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
   const qgl::SearchLds L = qgl::search_lds(D, R, a.ef_cap, GV ? 0 : (1 << a.hash_bits), a.k_cap);
   uint8_t* lds = smem + wave * L.total;
+  uint8_t* mlp = smem + (blockDim.x >> 6) * L.total;  // after every wavefront's area
+  if constexpr (LS == kLsStop) {
+    stage_mlp(a.ls_w, mlp);
+    __syncthreads();
+  }
   const int wid = blockIdx.x * (blockDim.x >> 6) + wave;
   uint32_t* gbits = GV ? a.fb_bits + (int64_t)wid * a.fb_words : nullptr;
   int* ctr = a.counters + (GV ? 2 : 0);
@@ -760,7 +829,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
     qi = __shfl(qi, 0, 64);
     if (qi >= limit) break;
     const int64_t q = GV ? (int64_t)a.overflow_list[qi] : (int64_t)qi;
-    search_one<D, R, GV, LS>(a, q, lds, L, gbits);
+    search_one<D, R, GV, LS>(a, q, lds, L, gbits, mlp);
   }
 }
 
@@ -821,7 +890,7 @@ hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, con
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV, bool LS>
+template <int D, int R, bool GV, int LS>
 static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t lds, hipStream_t st) {
   auto kern = search_kernel<D, R, GV, LS>;
   if (lds > 64 * 1024) {
@@ -833,7 +902,7 @@ static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV, bool LS>
+template <int D, int R, bool GV, int LS>
 static int occupancy_t(int wpb, size_t lds) {
   int nb = 0;
   auto kern = search_kernel<D, R, GV, LS>;
@@ -844,30 +913,42 @@ static int occupancy_t(int wpb, size_t lds) {
   return nb;
 }
 
-hipError_t launch_search(int D, int R, bool overflow_pass, bool learned_stop, const SearchArgs& a, int grid, int wpb,
+hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const SearchArgs& a, int grid, int wpb,
                          size_t lds, hipStream_t st) {
-#define QG_CASE(d, r)                                                                                  \
-  if (D == d && R == r) {                                                                              \
-    if (learned_stop)                                                                                  \
-      return overflow_pass ? launch_search_t<d, r, true, true>(a, grid, wpb, lds, st)                  \
-                           : launch_search_t<d, r, false, true>(a, grid, wpb, lds, st);                \
-    return overflow_pass ? launch_search_t<d, r, true, false>(a, grid, wpb, lds, st)                   \
-                         : launch_search_t<d, r, false, false>(a, grid, wpb, lds, st);                 \
+#define QG_LS(d, r, gv)                                                             \
+  switch (ls_mode) {                                                                \
+    case kLsOff: return launch_search_t<d, r, gv, kLsOff>(a, grid, wpb, lds, st);     \
+    case kLsStop: return launch_search_t<d, r, gv, kLsStop>(a, grid, wpb, lds, st);   \
+    case kLsTrace: return launch_search_t<d, r, gv, kLsTrace>(a, grid, wpb, lds, st); \
+    default: return hipErrorInvalidValue;                                           \
+  }
+#define QG_CASE(d, r)                  \
+  if (D == d && R == r) {              \
+    if (overflow_pass) QG_LS(d, r, true) \
+    QG_LS(d, r, false)                 \
   }
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
+#undef QG_LS
   return hipErrorInvalidValue;
 }
 
-int search_occupancy(int D, int R, bool overflow_pass, bool learned_stop, int wpb, size_t lds) {
-#define QG_CASE(d, r)                                                                                   \
-  if (D == d && R == r) {                                                                               \
-    if (learned_stop)                                                                                   \
-      return overflow_pass ? occupancy_t<d, r, true, true>(wpb, lds) : occupancy_t<d, r, false, true>(wpb, lds); \
-    return overflow_pass ? occupancy_t<d, r, true, false>(wpb, lds) : occupancy_t<d, r, false, false>(wpb, lds);  \
+int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, size_t lds) {
+#define QG_LS(d, r, gv)                                                   \
+  switch (ls_mode) {                                                      \
+    case kLsOff: return occupancy_t<d, r, gv, kLsOff>(wpb, lds);            \
+    case kLsStop: return occupancy_t<d, r, gv, kLsStop>(wpb, lds);          \
+    case kLsTrace: return occupancy_t<d, r, gv, kLsTrace>(wpb, lds);        \
+    default: return 0;                                                    \
+  }
+#define QG_CASE(d, r)                  \
+  if (D == d && R == r) {              \
+    if (overflow_pass) QG_LS(d, r, true) \
+    QG_LS(d, r, false)                 \
   }
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
+#undef QG_LS
   return 0;
 }
 

@@ -89,7 +89,7 @@ def pick_theta(idx, queries: torch.Tensor, gt: torch.Tensor, mlp_bits: torch.Ten
     """Largest stopping eagerness (smallest theta) whose recall on these queries reaches target.
     Returns (theta, recall, mean expansions) or None."""
     best = None
-    for th in (grid if grid is not None else (6.0, 4.0, 3.0, 2.0, 1.5, 1.0, 0.5, 0.0, -0.5, -1.0, -2.0)):
+    for th in (grid if grid is not None else [6.0 - 0.25 * i for i in range(33)]):
         ids, _, st, _ = idx.search_stop(queries, k, ef, mlp_bits, theta=th, t_min=t_min, t_every=t_every,
                                         stats=True)
         r = recall_rows(ids, gt).mean().item()

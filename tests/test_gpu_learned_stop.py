@@ -91,6 +91,32 @@ def test_stop_decisions_parity(small):
         assert np.array_equal(o[i, :cnt[i]], oo2[i, :cnt[i]]), f"MLP outputs differ, query {i}"
 
 
+@pytest.mark.parametrize("k,ef,t_min,t_every", [(10, 64, 6, 2), (1, 1, 1, 1), (20, 128, 3, 5)])
+def test_stop_only_parity(small, k, ef, t_min, t_every):
+    """Without a trace the kernel keeps the MLP in LDS (a separate code path);
+    ids, distances and counters still match the oracle, and the stop fires for
+    some queries."""
+    c = small
+    w = _mlp_bits(11)
+    _, _, _, (_, _, oo, oc) = oracle.search_ls(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], k, ef, w=w,
+                                               theta=np.inf, t_min=t_min, t_every=t_every, max_evals=256)
+    outs = np.concatenate([oo[i, :oc[i]] for i in range(len(oc))])
+    theta = float(np.quantile(outs, 0.7)) if outs.size else 0.0
+    wd = torch.from_numpy(w.view(np.int16)).to(DEV)
+    print(f"stop-only k={k} ef={ef} theta={theta:.4f}", flush=True)
+    ids, d, st, tr = c["idx"].search_stop(T(c["Q"]), k, ef, wd, theta=theta, t_min=t_min, t_every=t_every,
+                                          stats=True)
+    torch.cuda.synchronize()
+    assert tr is None
+    oi, od, ost, _ = oracle.search_ls(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], k, ef, w=w, theta=theta,
+                                      t_min=t_min, t_every=t_every)
+    assert np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(d.cpu().numpy(), od)
+    assert np.array_equal(st.cpu().numpy()[:, :3], ost[:, :3])
+    if ef > 1:
+        plain = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], k, ef, with_stats=True)
+        assert (ost[:, 0] < plain[2][:, 0]).any()
+
+
 def test_training_pipeline_runs(small):
     """Traces -> labels -> MLP -> bf16 export -> theta: the trained stop cuts
     expansions while keeping recall close to the plain search."""
