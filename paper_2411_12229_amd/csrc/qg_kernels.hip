@@ -57,31 +57,70 @@ __device__ __forceinline__ float unsortable(uint32_t s) {
 }
 __device__ __forceinline__ uint64_t pack_kv(float key, uint32_t id) { return ((uint64_t)sortable(key) << 32) | id; }
 
-__device__ __forceinline__ float wave_max(float v) {
-  for (int s = 32; s >= 1; s >>= 1) v = fmaxf(v, __shfl_xor(v, s, 64));
-  return v;
+// Minimum over the wavefront of an unsigned value, through DPP: within each
+// row of 16 lanes by quad permutes and row rotations, then across rows by the
+// row broadcasts of lanes 15 and 31; lane 63 ends with the minimum.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t v) {
+  const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFFu, (int)v, CTRL, ROWS, 0xF, false);
+  return o < v ? o : v;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = dpp_min_step<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v = dpp_min_step<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v = dpp_min_step<0x124, 0xF>(v);  // row_ror:4
+  v = dpp_min_step<0x128, 0xF>(v);  // row_ror:8
+  v = dpp_min_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_min_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// x from lane (lane ^ s).  s = 1, 2: DPP quad permutes; 4, 8, 16: LDS swizzle
-// in bit mode (xor within 32 lanes); 32: bpermute.  Pure data movement, so a
-// butterfly built on it adds exactly p[l] + p[l^s].
+// x from lane (lane ^ s) for s = 1, 2 (DPP quad permutes) and 4, 8, 16 (LDS
+// swizzle in bit mode, xor within 32 lanes).  Pure data movement.
 template <int S>
-__device__ __forceinline__ float xor_lane(float x) {
-  const int v = __float_as_int(x);
-  if constexpr (S == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));
-  if constexpr (S == 2) return __int_as_float(__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));
-  if constexpr (S == 4 || S == 8 || S == 16) return __int_as_float(__builtin_amdgcn_ds_swizzle(v, (S << 10) | 0x1F));
-  return __shfl_xor(x, 32, 64);
+__device__ __forceinline__ int xor_lane_i(int v) {
+  static_assert(S == 1 || S == 2 || S == 4 || S == 8 || S == 16, "xor distance");
+  if constexpr (S == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  if constexpr (S == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  return __builtin_amdgcn_ds_swizzle(v, (S << 10) | 0x1F);
+}
+template <int S>
+__device__ __forceinline__ float xor_lane(float x) { return __int_as_float(xor_lane_i<S>(__float_as_int(x))); }
+
+// The pair {x[l], x[l ^ 32]} in every lane l, through the gfx950 lane swap of
+// the two wavefront halves (which of the two comes first depends on the half;
+// only symmetric combinations of the pair are used).
+__device__ __forceinline__ void pair32(float x, float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
 }
 
+// Butterfly sum p[l] + p[l ^ s] for s = 32, 16, ..., 1; every lane ends with
+// the total.  Floating-point addition is commutative, so each stage adds
+// exactly the pair the stage names whatever the order within the pair.
 __device__ __forceinline__ float butterfly_f(float p) {
-  p = p + xor_lane<32>(p);
+  float a, b;
+  pair32(p, a, b);
+  p = a + b;
   p = p + xor_lane<16>(p);
   p = p + xor_lane<8>(p);
   p = p + xor_lane<4>(p);
   p = p + xor_lane<2>(p);
   p = p + xor_lane<1>(p);
   return p;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  float a, b;
+  pair32(v, a, b);
+  v = fmaxf(a, b);
+  v = fmaxf(v, xor_lane<16>(v));
+  v = fmaxf(v, xor_lane<8>(v));
+  v = fmaxf(v, xor_lane<4>(v));
+  v = fmaxf(v, xor_lane<2>(v));
+  v = fmaxf(v, xor_lane<1>(v));
+  return v;
 }
 
 // Exact squared distance |q - x|^2 (implicit re-ranking, Sec. 3.1.2): dim i
@@ -300,7 +339,7 @@ struct BlockView {
         s += base[row * 16 + ((cw[w] >> (4 * t)) & 15u)];
       }
     }
-    if constexpr (LPN == 2) s += __shfl_xor(s, 1, 64);
+    if constexpr (LPN == 2) s += xor_lane_i<1>(s);
     return s;
   }
 };
@@ -342,7 +381,7 @@ __device__ __forceinline__ bool visited_insert(const Visited& v, uint32_t id, in
   if constexpr (GV) {
     uint32_t old = 0;
     if (lane == 0) old = atomicOr(v.bits + (id >> 5), 1u << (id & 31));
-    old = __shfl(old, 0, 64);
+    old = (uint32_t)__builtin_amdgcn_readlane((int)old, 0);
     return (old >> (id & 31)) & 1u;
   } else {
     uint32_t base = v.slot0(id);
@@ -630,14 +669,11 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     // unchecked old entry; prefetch its block unless it is already visited
     uint64_t best = kNone;
     if (nv > 0) {
-      uint64_t mine = valid ? cand : kNone;
-#pragma unroll
-      for (int sft = 32; sft >= 1; sft >>= 1) {
-        const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(mine >> 32), sft, 64) << 32) |
-                           (uint32_t)__shfl_xor((int)(uint32_t)mine, sft, 64);
-        mine = o < mine ? o : mine;
-      }
-      best = ((uint64_t)uni((uint32_t)(mine >> 32)) << 32) | uni((uint32_t)mine);
+      const uint32_t hk = wave_min_u32(valid ? (uint32_t)(cand >> 32) : 0xFFFFFFFFu);
+      const uint64_t tie = ballot(valid && (uint32_t)(cand >> 32) == hk);
+      const uint32_t lo = (tie & (tie - 1)) ? wave_min_u32((tie >> lane) & 1 ? (uint32_t)cand : 0xFFFFFFFFu)
+                                            : rdlane((uint32_t)cand, first_lane(tie));
+      best = ((uint64_t)hk << 32) | lo;
     }
     if (!o2_known) {
       for (int base = cursor; base < size; base += 64) {
@@ -701,28 +737,58 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 
     if (nv > 0) {
       // Merge, truncated to ef: old entry i moves to i + cnt_i (cnt_i = number of
-      // candidates strictly before it); the candidate of rank r lands at r + lb
-      // (lb = number of old entries <= it, so an old entry precedes an equal new
-      // one).  Candidates are broadcast from their lanes through scalar
-      // registers; all old entries are read before any is written.
+      // candidates strictly before it); the candidate of rank r lands at r + lb_r
+      // (lb_r = number of old entries <= it, so an old entry precedes an equal
+      // new one).  The candidates are compacted into LDS and read back at
+      // uniform addresses (broadcast reads); all old entries are read before
+      // any is written.
+      uint64_t* cbuf = reinterpret_cast<uint64_t*>(lds + L.cand);
+      int32_t* lbarr = reinterpret_cast<int32_t*>(lds + L.cand);  // reused once the ranks are known
+      if (valid) cbuf[lanes_below(V)] = cand;
+      if (lane < 4) cbuf[nv + lane] = kNone;  // padding: compares below nothing
+      wave_sync();
+      const int nv4 = (nv + 3) & ~3;
       int sidx = 0;  // rank of this lane's candidate
-      int lbv = 0;   // lb of this lane's candidate
+      int lbv;       // lb of this lane's candidate
       if (size <= 128) {
         const bool live0 = lane < size, live1 = lane + 64 < size;
-        const uint64_t e0 = live0 ? beam[lane] : 0ull, e1 = live1 ? beam[lane + 64] : 0ull;
+        const uint64_t e0 = live0 ? beam[lane] : kNone, e1 = live1 ? beam[lane + 64] : kNone;
         const uint64_t k0 = e0 & ~(uint64_t)kChecked, k1 = e1 & ~(uint64_t)kChecked;
-        const uint64_t L0 = ballot(live0), L1 = ballot(live1);
         int c0 = 0, c1 = 0;
-        for (uint64_t mm = V; mm; mm &= mm - 1) {
-          const int t = first_lane(mm);
-          const uint64_t ct = rdlane64(cand, t);
-          const bool lt0 = ct < k0, lt1 = ct < k1;
-          c0 += lt0;
-          c1 += lt1;
-          sidx += ct < cand;
-          const int le = __popcll(L0 & ~ballot(lt0)) + __popcll(L1 & ~ballot(lt1));
-          lbv = (lane == t) ? le : lbv;
+        if (size > 64) {
+          for (int t = 0; t < nv4; t += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const uint64_t ct = cbuf[t + u];
+              c0 += ct < k0;
+              c1 += ct < k1;
+              sidx += ct < cand;
+            }
+          }
+        } else {
+          for (int t = 0; t < nv4; t += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const uint64_t ct = cbuf[t + u];
+              c0 += ct < k0;
+              sidx += ct < cand;
+            }
+          }
         }
+        // lb from the counts: the candidates of ranks [cnt_{i-1}, cnt_i) come
+        // right before old entry i (cnt_{-1} = 0); ranks from cnt_{size-1} on
+        // come after every old entry
+        // cnt of the entry before (DPP wave_shr:1; lane 0 keeps the old value 0)
+        int p0 = __builtin_amdgcn_update_dpp(0, c0, 0x138, 0xF, 0xF, false);
+        int p1 = __builtin_amdgcn_update_dpp(0, c1, 0x138, 0xF, 0xF, false);
+        if (lane == 0) p1 = (int)rdlane((uint32_t)c0, 63);
+        if (live0)
+          for (int r = p0; r < c0; ++r) lbarr[r] = lane;
+        if (live1)
+          for (int r = p1; r < c1; ++r) lbarr[r] = lane + 64;
+        const int clast = size > 64 ? (int)rdlane((uint32_t)c1, size - 65) : (int)rdlane((uint32_t)c0, size - 1);
+        wave_sync();
+        lbv = (valid && sidx < clast) ? lbarr[sidx] : size;
         const int np0 = lane + c0, np1 = lane + 64 + c1;
         const uint64_t t0m = ballot(live0 && np0 == ef - 1), t1m = ballot(live1 && np1 == ef - 1);
         if (t0m) tail = rdlane64(k0, first_lane(t0m));
@@ -730,20 +796,21 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         if (live0 && np0 < ef) beam[np0] = e0;
         if (live1 && np1 < ef) beam[np1] = e1;
       } else {
-        for (uint64_t mm = V; mm; mm &= mm - 1) sidx += rdlane64(cand, first_lane(mm)) < cand;
+        const int ci = lanes_below(V);
+        for (int j = 0; j < nv4; ++j) sidx += cbuf[j] < cand;
+        lbv = 0;
         for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {  // top down
           const int i = base + lane;
           const bool live = i < size;
-          const uint64_t e = live ? beam[i] : 0ull;
+          const uint64_t e = live ? beam[i] : kNone;
           const uint64_t ke = e & ~(uint64_t)kChecked;
           const uint64_t Lm = ballot(live);
           int cnt = 0;
-          for (uint64_t mm = V; mm; mm &= mm - 1) {
-            const int t = first_lane(mm);
-            const bool lt = rdlane64(cand, t) < ke;
+          for (int j = 0; j < nv; ++j) {
+            const bool lt = cbuf[j] < ke;
             cnt += lt;
             const int le = __popcll(Lm & ~ballot(lt));
-            lbv += (lane == t) ? le : 0;
+            lbv += (ci == j) ? le : 0;
           }
           const int np = i + cnt;
           const uint64_t tm = ballot(live && np == ef - 1);
@@ -756,7 +823,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       const uint64_t tm = ballot(valid && npos == ef - 1);
       if (tm) tail = rdlane64(cand, first_lane(tm));
       wave_sync();
-      const int first = uni(__shfl(npos, first_lane(ballot(valid && sidx == 0)), 64));
+      const int first = (int)rdlane((uint32_t)npos, first_lane(ballot(valid && sidx == 0)));
       if (first < cursor) cursor = first;
       size = (size + nv < ef) ? size + nv : ef;
     }
@@ -809,7 +876,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 template <int D, int R, bool GV, int LS>
 __global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const int wave = threadIdx.x >> 6;
+  const int wave = uni((int)(threadIdx.x >> 6));
   const int lane = lane_id();
   const qgl::SearchLds L = qgl::search_lds(D, R, a.ef_cap, GV ? 0 : (1 << a.hash_bits), a.k_cap);
   uint8_t* lds = smem + wave * L.total;
@@ -826,7 +893,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
   for (;;) {
     int qi = 0;
     if (lane == 0) qi = atomicAdd(ctr, 1);
-    qi = __shfl(qi, 0, 64);
+    qi = __builtin_amdgcn_readlane(qi, 0);
     if (qi >= limit) break;
     const int64_t q = GV ? (int64_t)a.overflow_list[qi] : (int64_t)qi;
     search_one<D, R, GV, LS>(a, q, lds, L, gbits, mlp);

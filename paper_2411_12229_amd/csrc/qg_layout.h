@@ -24,7 +24,7 @@ __host__ __device__ constexpr int off_nbr(int D, int R) { return off_fadd(D, R) 
 // Per-wavefront LDS of the search kernel (bytes).  ef_cap and k_cap are
 // multiples of 4 so every piece stays 16-byte aligned.
 struct SearchLds {
-  int lut, beam, hash, nkey, nid, total;
+  int lut, beam, cand, hash, nkey, nid, total;
 };
 
 __host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
@@ -34,12 +34,16 @@ __host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
 // wavefront read different LDS banks.
 __host__ __device__ constexpr int lut_rows_padded(int D, int R) { return D / 4 + (64 / R) - 1; }
 
-// beam: (key bits, id | checked) pairs kept sorted; hash: visited ids;
-// nkey/nid: the k nearest vertices found so far.
+// cand: one expansion's candidates (R words + 4 of padding), reused for their
+// insertion points; beam: packed (key, id | checked) words kept sorted; hash:
+// visited ids; nkey/nid: the k nearest vertices found so far.  The pieces
+// indexed by lane (LUT, candidates, beam) come first, at offsets fixed by D
+// and R, so one address register serves them with immediate offsets.
 __host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int hash_cap, int k_cap) {
   SearchLds s{};
   int o = 0;
   s.lut = o;   o += align16(lut_rows_padded(D, R) * 32);
+  s.cand = o;  o += 8 * (R + 4);
   s.beam = o;  o += 8 * ef_cap;
   s.hash = o;  o += 4 * hash_cap;
   s.nkey = o;  o += 4 * k_cap;
