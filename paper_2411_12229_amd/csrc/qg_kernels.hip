@@ -146,20 +146,43 @@ __device__ __forceinline__ float exact_dist(const float (&qv)[DPL], const float 
 __global__ __launch_bounds__(64) void rotate_kernel(const float* __restrict__ in, int64_t n, int D,
                                                     const float* __restrict__ M, float* __restrict__ out,
                                                     int* __restrict__ zero, int nzero) {
+  // the tile's 16 input rows and 16 rows of M, 128 columns at a time, staged
+  // through LDS with coalesced loads (rows padded to 132 floats)
+  constexpr int KC = 128, LD = KC + 4;
+  __shared__ float As[16 * LD], Bs[16 * LD];
   const int lane = threadIdx.x;
   if (zero && blockIdx.x == 0 && blockIdx.y == 0 && lane < nzero) zero[lane] = 0;
   const int64_t r0 = (int64_t)blockIdx.x * 16;
   const int i0 = blockIdx.y * 16;
-  const int64_t ra = r0 + (lane & 15);
-  const int kk = lane >> 4;
-  const float* arow = in + (ra < n ? ra : 0) * (int64_t)D;
-  const float* brow = M + (int64_t)(i0 + (lane & 15)) * D;
-  const bool rok = ra < n;
+  const int rl = lane & 15, kk = lane >> 4;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int kb = 0; kb < D; kb += 4) {
-    double a = rok ? (double)arow[kb + kk] : 0.0;
-    double b = (double)brow[kb + kk];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  for (int k0 = 0; k0 < D; k0 += KC) {
+    const int kw = D - k0 < KC ? D - k0 : KC;  // a multiple of 16
+    // every load of the chunk is issued before the first store; columns past
+    // kw re-read column kw - 1 and land in the unread part of the row
+    float va[16][2], vb[16][2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t ra = r0 + r < n ? r0 + r : 0;  // rows past n only feed outputs that are not stored
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = min(lane + 64 * h, kw - 1);
+        va[r][h] = in[ra * D + k0 + c];
+        vb[r][h] = M[(int64_t)(i0 + r) * D + k0 + c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        As[r * LD + lane + 64 * h] = va[r][h];
+        Bs[r * LD + lane + 64 * h] = vb[r][h];
+      }
+    __syncthreads();
+    for (int kb = 0; kb < kw; kb += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)As[rl * LD + kb + kk], (double)Bs[rl * LD + kb + kk], acc,
+                                                 0, 0, 0);
+    __syncthreads();
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -289,6 +312,43 @@ __device__ __forceinline__ float build_lut(const float* __restrict__ qrot, int16
 
 // Vertex block fields as one lane sees them: its dims of the raw vector, its
 // share of one neighbour's code, that neighbour's factors and id.
+// LDS (address space 3) views: 32-bit byte addresses of shared memory.
+typedef __attribute__((address_space(3))) const int16_t lds_i16;
+__device__ __forceinline__ uint32_t lds_addr(const int16_t* p) {
+  return (uint32_t)(uintptr_t)(lds_i16*)p;  // generic -> LDS address-space cast
+}
+
+// base + byte K of x in one instruction (SDWA source select).
+template <int K>
+__device__ __forceinline__ uint32_t add_byte(uint32_t base, uint32_t x) {
+  uint32_t r;
+  if constexpr (K == 0)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r) : "v"(base), "v"(x));
+  else if constexpr (K == 1)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+        : "=v"(r) : "v"(base), "v"(x));
+  else if constexpr (K == 2)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+        : "=v"(r) : "v"(base), "v"(x));
+  else
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+        : "=v"(r) : "v"(base), "v"(x));
+  return r;
+}
+
+// Sum of the LUT entries of nibbles T .. N-1 of one code unit: nibble t of
+// the unit indexes row t, at byte (t >> 1) of ev (even t) or od (odd t).
+template <int T, int N>
+__device__ __forceinline__ int lut_sum(uint32_t b8, uint32_t ev, uint32_t od) {
+  const uint32_t a = add_byte<(T >> 1)>(b8, (T & 1) ? od : ev);
+  const int v = *(lds_i16*)(uintptr_t)(a + T * 32);
+  if constexpr (T + 1 < N)
+    return v + lut_sum<T + 1, N>(b8, ev, od);
+  else
+    return v;
+}
+
 template <int D, int R>
 struct BlockView {
   static constexpr int LPN = 64 / R;        // lanes per neighbour
@@ -330,14 +390,14 @@ struct BlockView {
     constexpr int UNIT_NIB = WORDS ? 8 : 4;
     const int h = lane % LPN;
     const int16_t* base = lut + (h * RPG + h) * 16;  // group h starts after h padding rows
+    const uint32_t b8 = lds_addr(base);
     int s = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-#pragma unroll
-      for (int t = 0; t < UNIT_NIB; ++t) {
-        const int row = w * UNIT_NIB + t;
-        s += base[row * 16 + ((cw[w] >> (4 * t)) & 15u)];
-      }
+      // byte offsets (2 x nibble) of the even and odd nibbles, one per byte:
+      // each lookup address is the base plus one byte of a register
+      const uint32_t ev = (cw[w] << 1) & 0x1E1E1E1Eu, od = (cw[w] >> 3) & 0x1E1E1E1Eu;
+      s += lut_sum<0, UNIT_NIB>(b8 + w * UNIT_NIB * 32, ev, od);
     }
     if constexpr (LPN == 2) s += xor_lane_i<1>(s);
     return s;
@@ -605,36 +665,58 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   int since = 0, nevals = 0;  // learned stop: expansions since NN changed, evaluations so far
 
   for (;;) {
-    // pop the first unchecked entry; the same chunk read gives the next
-    // unchecked entry after it (o2)
+    // pop the first unchecked entry whose vertex is not visited yet.  Unchecked
+    // entries before it are further estimates of visited vertices: popping
+    // them only marks them checked, so they are consumed here in one step (each
+    // counts as a pop).  The same chunk read gives the next unchecked entry
+    // (o2u, for the stop features) and the next one still to be expanded (o2f,
+    // the prefetch target).
     int c = -1;
     uint32_t p = 0;
-    uint64_t o2 = kNone;
-    bool o2_known = false;
+    uint64_t o2u = kNone, o2f = kNone;
+    bool o2u_known = false, o2f_known = false;
     while (cursor < size) {
       const int i = cursor + lane;
       const uint64_t e = (i < size) ? beam[i] : (uint64_t)kChecked;
-      const uint64_t m = ballot(!((uint32_t)e & kChecked));
-      if (m) {
-        const int f = first_lane(m);
-        c = cursor + f;
-        p = rdlane((uint32_t)e, f);
-        const uint64_t m2 = m & (m - 1);
-        if (m2) {
-          o2 = rdlane64(e, first_lane(m2));
-          o2_known = true;
-        } else {
-          o2_known = cursor + 64 >= size;  // nothing unchecked after c
-        }
-        break;
+      const bool un = !((uint32_t)e & kChecked);
+      const uint64_t mu = ballot(un);
+      if (!mu) {
+        cursor += 64;
+        continue;
       }
-      cursor += 64;
+      bool fresh = false;
+      if (un) fresh = !visited_contains<GV>(vis, (uint32_t)e);
+      const uint64_t mf = ballot(fresh);
+      const uint64_t dups = mf ? mu & ((1ull << first_lane(mf)) - 1) : mu;
+      if (dups) {
+        if ((dups >> lane) & 1) beam_lo[2 * i] = (uint32_t)e | kChecked;
+        pops += __popcll(dups);
+      }
+      if (!mf) {
+        cursor += 64;
+        continue;
+      }
+      const int f = first_lane(mf);
+      c = cursor + f;
+      p = rdlane((uint32_t)e, f);
+      const uint64_t later = f == 63 ? 0ull : ~0ull << (f + 1);
+      const uint64_t mu2 = mu & later, mf2 = mf & later & ballot((uint32_t)e != p);
+      if (mu2) {
+        o2u = rdlane64(e, first_lane(mu2));
+        o2u_known = true;
+      }
+      if (mf2) {
+        o2f = rdlane64(e, first_lane(mf2));
+        o2f_known = true;
+      }
+      if (cursor + 64 >= size) o2u_known = o2f_known = true;  // nothing after this chunk
+      break;
     }
     if (c < 0) break;
     beam_lo[2 * c] = p | kChecked;  // every lane stores the same word
     cursor = c + 1;
     ++pops;
-    if (visited_insert<GV>(vis, p, lane)) continue;  // a second estimate of a visited vertex
+    visited_insert<GV>(vis, p, lane);  // p is not in the set: a new slot
     if (++nvis > vis_limit) {  // on-chip visited set full: hand the query to the overflow path
       if (lane == 0) {
         const int slot = atomicAdd(a.counters + 1, 1);
@@ -665,8 +747,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const uint64_t V = ballot(valid);
     const int nv = uni((int)__popcll(V));
 
-    // best candidate, then the next pop: the smaller of it and the first
-    // unchecked old entry; prefetch its block unless it is already visited
+    // best candidate (the smallest (estimate, id) among them)
     uint64_t best = kNone;
     if (nv > 0) {
       const uint32_t hk = wave_min_u32(valid ? (uint32_t)(cand >> 32) : 0xFFFFFFFFu);
@@ -675,25 +756,38 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
                                             : rdlane((uint32_t)cand, first_lane(tie));
       best = ((uint64_t)hk << 32) | lo;
     }
-    if (!o2_known) {
-      for (int base = cursor; base < size; base += 64) {
+    // o2f (and o2u, for the stop features) beyond the popped chunk
+    if (!o2f_known || (LS != kLsOff && !o2u_known)) {
+      for (int base = cursor; base < size && !(o2f_known && (LS == kLsOff || o2u_known)); base += 64) {
         const int i = base + lane;
         const uint64_t e = (i < size) ? beam[i] : (uint64_t)kChecked;
-        const uint64_t m = ballot(!((uint32_t)e & kChecked));
-        if (m) {
-          o2 = rdlane64(e, first_lane(m));
-          break;
+        const bool un = !((uint32_t)e & kChecked);
+        const uint64_t mu = ballot(un);
+        if (!mu) continue;
+        if (LS != kLsOff && !o2u_known) {
+          o2u = rdlane64(e, first_lane(mu));
+          o2u_known = true;
+        }
+        if (!o2f_known) {
+          bool fresh = false;
+          if (un) fresh = !visited_contains<GV>(vis, (uint32_t)e);
+          const uint64_t mf = ballot(fresh);
+          if (mf) {
+            o2f = rdlane64(e, first_lane(mf));
+            o2f_known = true;
+          }
         }
       }
     }
-    const uint64_t nxt_kv = best < o2 ? best : o2;  // the entry popped next
-    const float bfk = nxt_kv == kNone ? __builtin_inff() : unsortable((uint32_t)(nxt_kv >> 32));
-    if (nxt_kv != kNone) {
-      const uint32_t nx = (uint32_t)nxt_kv & kIdMask;
-      if (!visited_contains<GV>(vis, nx)) {
-        nxt.load(a.blocks + (int64_t)nx * a.block_bytes, lane);
-        nxt_id = nx;
-      }
+    // the next pop is the smaller of the best candidate and o2u; the next
+    // expansion the smaller of the best candidate and o2f: prefetch its block
+    const uint64_t nxt_u = best < o2u ? best : o2u;
+    const float bfk = nxt_u == kNone ? __builtin_inff() : unsortable((uint32_t)(nxt_u >> 32));
+    const uint64_t nxt_f = best < o2f ? best : o2f;
+    if (nxt_f != kNone) {
+      const uint32_t nx = (uint32_t)nxt_f & kIdMask;
+      nxt.load(a.blocks + (int64_t)nx * a.block_bytes, lane);
+      nxt_id = nx;
     }
 
     // implicit re-ranking: NN keeps the k smallest (distance, id) seen
