@@ -118,6 +118,20 @@ typedef struct qg_stop_params {
 int qg_search_stop(const qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                    const qg_stop_params *stop, int32_t *out_ids, float *out_dists, int32_t *out_stats);
 
+/* Algorithm 1 with a result count and beam size of its own for every query,
+ * in one launch (queries of a mixed batch do not wait for the slowest
+ * setting).  k_per_query[nq] and ef_per_query[nq] are int32 device arrays;
+ * k_max and ef_max bound them (1 <= k_max <= QG_MAX_K, 1 <= ef_max <=
+ * QG_MAX_EF) and size on-chip memory for the whole batch.  out_ids and
+ * out_dists are [nq][k_max] (row stride k_max): row q holds its k_q results
+ * ascending by (distance, id), then (-1, +inf).  A query with k_q or ef_q
+ * outside [1, k_max] or [1, ef_max] is not searched: its row is all padding
+ * and, when out_stats is given, its counters are (0, 0, 0, -1).  Each
+ * query's results are those of qg_search_ex with its own k_q and ef_q. */
+int qg_search_mixed(const qg_index *idx, const float *queries, int64_t nq, const int32_t *k_per_query,
+                    const int32_t *ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags, int32_t *out_ids,
+                    float *out_dists, int32_t *out_stats);
+
 /* out[n][d] = M in[n][d] for the index's rotation M (Eq. rotation), on the
  * matrix cores: fp64 products accumulated over j ascending, rounded once to
  * fp32.  This is the first step of qg_search, exposed for checking. */
@@ -134,8 +148,19 @@ int qg_estimate(const qg_index *idx, const float *queries, const int32_t *vertex
 /* Copy blocks [first, first + count) (block_bytes each) to device memory dst. */
 int qg_copy_blocks(const qg_index *idx, int64_t first, int64_t count, void *dst);
 
-/* Select the HIP stream (hipStream_t) for later work; NULL = null stream. */
+/* Select the HIP stream (hipStream_t) for later work; NULL = null stream.
+ * Every search call only enqueues kernels on this stream (no host
+ * synchronisation, no memset), so a caller may record searches into a HIP
+ * graph by capturing this stream.  Calls on one index share its scratch and
+ * must not overlap in time on different streams. */
 int qg_set_stream(qg_index *idx, void *hip_stream);
+
+/* Grow the index's per-query scratch (rotated queries, overflow list) to hold
+ * at least nq queries.  Searches grow it themselves (reallocating) when a
+ * batch is larger than any before; captured graphs refer to the scratch that
+ * existed at capture time, so reserve the largest batch before capturing and
+ * replay only while no later call has grown it.  Synchronous. */
+int qg_reserve(qg_index *idx, int64_t nq);
 
 /* Index geometry; any output pointer may be NULL. Host pointers. */
 int qg_index_info(const qg_index *idx, int64_t *n, int32_t *d, int32_t *r, int32_t *entry, int64_t *block_bytes);

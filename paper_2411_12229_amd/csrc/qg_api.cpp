@@ -374,8 +374,11 @@ int qg_rotate(const qg_index* idx, const float* in, int64_t n, float* out) {
   return QG_OK;
 }
 
-int qg_search_stop(const qg_index* cidx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
-                   const qg_stop_params* stop, int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+// Every search entry point ends here.  k and ef are the values of a uniform
+// batch, or the bounds of a mixed one (k_q, ef_q: per-query device arrays).
+static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, int32_t k, int32_t ef,
+                       const int32_t* k_q, const int32_t* ef_q, int32_t flags, const qg_stop_params* stop,
+                       int32_t* out_ids, float* out_dists, int32_t* out_stats) {
   qg_index* idx = const_cast<qg_index*>(cidx);
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (nq < 0) return fail(QG_EINVAL, "nq < 0");
@@ -412,6 +415,9 @@ int qg_search_stop(const qg_index* cidx, const float* queries, int64_t nq, int32
   a.nq = nq;
   a.k = k;
   a.ef = ef;
+  a.k_q = k_q;
+  a.ef_q = ef_q;
+  a.k_out = k;
   a.k_cap = k_cap;
   a.ef_cap = ef_cap;
   a.hash_bits = hbits;
@@ -462,6 +468,26 @@ int qg_search_stop(const qg_index* cidx, const float* queries, int64_t nq, int32
   HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, a, idx->fb_slots, 1, (size_t)Lf.total + extra, idx->stream),
           "search overflow pass");
   return QG_OK;
+}
+
+int qg_search_stop(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                   const qg_stop_params* stop, int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+  return search_impl(idx, queries, nq, k, ef, nullptr, nullptr, flags, stop, out_ids, out_dists, out_stats);
+}
+
+int qg_search_mixed(const qg_index* idx, const float* queries, int64_t nq, const int32_t* k_per_query,
+                    const int32_t* ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags, int32_t* out_ids,
+                    float* out_dists, int32_t* out_stats) {
+  if (nq > 0 && (!k_per_query || !ef_per_query)) return fail(QG_EINVAL, "NULL per-query k or ef array");
+  return search_impl(idx, queries, nq, k_max, ef_max, k_per_query, ef_per_query, flags, nullptr, out_ids, out_dists,
+                     out_stats);
+}
+
+int qg_reserve(qg_index* idx, int64_t nq) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (nq < 0 || nq > 0x7fffffffLL) return fail(QG_EINVAL, "nq out of range");
+  DeviceGuard g(idx->device);
+  return ensure_scratch(idx, nq);
 }
 
 int qg_search_ex(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,

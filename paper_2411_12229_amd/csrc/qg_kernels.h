@@ -16,6 +16,9 @@ struct SearchArgs {
   int hash_bits;  // LDS visited hash holds 2^hash_bits ids
   int flags;
   int entry;
+  const int32_t* k_q;     // nullable: per-query k (then k is the bound)
+  const int32_t* ef_q;    // nullable: per-query ef (then ef is the bound)
+  int k_out;              // output row stride (k, or the bound of a mixed batch)
   int32_t* out_ids;
   float* out_dists;
   int32_t* out_stats;     // nullable, [nq][4]

@@ -612,7 +612,20 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   constexpr int LPN = BV::LPN;
   constexpr uint64_t kNone = ~0ull;  // sorts after every real entry
   const int lane = lane_id();
-  const int ef = a.ef, k = a.k;
+  int ef = a.ef, k = a.k;
+  if (a.ef_q) {
+    // a beam size and result count of its own; a.ef and a.k are the bounds
+    ef = uni(a.ef_q[q]);
+    k = uni(a.k_q[q]);
+    if (k < 1 || k > a.k || ef < 1 || ef > a.ef) {  // rejected: an all-padding row, stats[3] = -1
+      for (int i = lane; i < a.k_out; i += 64) {
+        a.out_ids[q * a.k_out + i] = -1;
+        a.out_dists[q * a.k_out + i] = __builtin_inff();
+      }
+      if (a.out_stats && lane < 4) a.out_stats[4 * q + lane] = lane == 3 ? -1 : 0;
+      return;
+    }
+  }
   int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
   // beam entries: sortable(key) << 32 | id | checked, kept in ascending order
   uint64_t* beam = reinterpret_cast<uint64_t*>(lds + L.beam);
@@ -950,9 +963,9 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   }
 
   // answer: NN ascending by (distance, id), padded with (-1, inf)
-  for (int i = lane; i < k; i += 64) {
-    a.out_ids[q * k + i] = i < nnc ? (int32_t)nid[i] : -1;
-    a.out_dists[q * k + i] = i < nnc ? nkey[i] : __builtin_inff();
+  for (int i = lane; i < a.k_out; i += 64) {  // k_out = k, or the row stride of a mixed batch
+    a.out_ids[q * a.k_out + i] = i < nnc ? (int32_t)nid[i] : -1;
+    a.out_dists[q * a.k_out + i] = i < nnc ? nkey[i] : __builtin_inff();
   }
   if (a.out_stats && lane == 0) {
     int32_t* st = a.out_stats + 4 * q;

@@ -53,10 +53,12 @@ def _load():
         "qg_search": ([P, P, i64, i32, i32, P, P], c_int),
         "qg_search_ex": ([P, P, i64, i32, i32, i32, P, P, P], c_int),
         "qg_search_stop": ([P, P, i64, i32, i32, i32, ctypes.POINTER(StopParams), P, P, P], c_int),
+        "qg_search_mixed": ([P, P, i64, P, P, i32, i32, i32, P, P, P], c_int),
         "qg_rotate": ([P, P, i64, P], c_int),
         "qg_estimate": ([P, P, P, i64, P, P, P], c_int),
         "qg_copy_blocks": ([P, i64, i64, P], c_int),
         "qg_set_stream": ([P, P], c_int),
+        "qg_reserve": ([P, i64], c_int),
         "qg_index_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)], c_int),
         "qg_timing": ([P, c_int], c_int),
@@ -117,6 +119,27 @@ class Index:
         """Run later work on a torch.cuda.Stream (None = null stream)."""
         self._stream = stream
         _check(_lib.qg_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)))
+
+    def reserve(self, nq: int) -> None:
+        """Size the query scratch for batches of up to nq queries (before capturing graphs)."""
+        _check(_lib.qg_reserve(self._h, int(nq)))
+
+    def search_mixed(self, queries: torch.Tensor, k: torch.Tensor, ef: torch.Tensor, k_max: int | None = None,
+                     ef_max: int | None = None, flags: int = 0, stats: bool = False):
+        """Algorithm 1 with a k and ef per query (int32 device tensors [nq]) in one launch ->
+        (ids [nq,k_max], dists [nq,k_max][, stats [nq,4]]); row q is its k_q results, then padding.
+        The bounds default to the tensors' maxima (one device-to-host read)."""
+        nq = queries.shape[0]
+        dev = queries.device
+        if k_max is None:
+            k_max = int(k.max().item()) if nq else 1
+        if ef_max is None:
+            ef_max = int(ef.max().item()) if nq else 1
+        ids = torch.empty((nq, k_max), dtype=torch.int32, device=dev)
+        dists = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=dev) if stats else None
+        qg_search_mixed(self, queries, nq, k, ef, k_max, ef_max, flags, ids, dists, st)
+        return (ids, dists, st) if stats else (ids, dists)
 
     def search(self, queries: torch.Tensor, k: int, ef: int, flags: int = 0, stats: bool = False):
         """Algorithm 1 for every row of `queries` -> (ids int32 [nq,k], dists f32 [nq,k][, stats int32 [nq,4]])."""
@@ -221,6 +244,22 @@ def qg_search_ex(idx: Index, queries, nq: int, k: int, ef: int, flags: int, out_
     st = _dev(out_stats, torch.int32, "out_stats") if out_stats is not None else None
     _check(_lib.qg_search_ex(idx.handle, _dev(queries, torch.float32, "queries"), nq, k, ef, flags,
                              _dev(out_ids, torch.int32, "out_ids"), _dev(out_dists, torch.float32, "out_dists"), st))
+
+
+def qg_search_mixed(idx: Index, queries, nq: int, k_per_query, ef_per_query, k_max: int, ef_max: int, flags: int,
+                    out_ids, out_dists, out_stats=None):
+    if queries.shape != (nq, idx.d) or out_ids.shape != (nq, k_max) or out_dists.shape != (nq, k_max):
+        raise ValueError("shape mismatch")
+    if k_per_query.shape != (nq,) or ef_per_query.shape != (nq,):
+        raise ValueError("per-query k and ef must be [nq]")
+    if out_stats is not None and out_stats.shape != (nq, 4):
+        raise ValueError("stats shape mismatch")
+    st = _dev(out_stats, torch.int32, "out_stats") if out_stats is not None else None
+    _check(_lib.qg_search_mixed(idx.handle, _dev(queries, torch.float32, "queries"), nq,
+                                _dev(k_per_query, torch.int32, "k_per_query"),
+                                _dev(ef_per_query, torch.int32, "ef_per_query"), k_max, ef_max, flags,
+                                _dev(out_ids, torch.int32, "out_ids"), _dev(out_dists, torch.float32, "out_dists"),
+                                st))
 
 
 def qg_search_stop(idx: Index, queries, nq: int, k: int, ef: int, flags: int, mlp, theta: float, t_min: int,

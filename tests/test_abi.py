@@ -38,4 +38,6 @@ def test_error_paths_without_device():
     assert lib.qg_load_index(b"/nonexistent/x.qgi", 0, ctypes.byref(out)) == -3
     assert b"cannot open" in lib.qg_last_error()
     assert lib.qg_search(None, None, 0, 10, 10, None, None) == -1
+    assert lib.qg_search_mixed(None, None, ctypes.c_int64(4), None, None, 10, 10, 0, None, None, None) == -1
+    assert lib.qg_reserve(None, ctypes.c_int64(10)) == -1
     lib.qg_free_index(None)

@@ -1,0 +1,144 @@
+"""One launch with a result count and beam size per query, and search calls
+captured into HIP graphs (through the C ABI).
+
+Bar: every query of a mixed batch returns exactly what the oracle returns for
+that query with its own k and ef (ids, distances bit-equal, counters equal),
+padded to the batch's row width; rejected (k, ef) give an all-padding row.
+Graph replays, with other device work between them, equal the eager results.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2411_12229_amd import qg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    X, Q = synth.gen_data(1)
+    M = synth.rotation(128, synth.seed(1, "rotation"))
+    G = synth.knn_graph(X, 32, synth.seed(1, "long"))
+    e = synth.medoid(X)
+    blocks = oracle.encode(X, G, M)
+    print("cfg1 index: N=10000 D=128 R=32", flush=True)
+    idx = qg.qg_build_index(T(X), T(G), T(M), e)
+    return dict(X=X, Q=Q, M=M, G=G, e=e, blocks=blocks, idx=idx)
+
+
+def _oracle_rows(c, Q, ks, efs, k_max):
+    ids = np.full((len(Q), k_max), -1, np.int32)
+    d = np.full((len(Q), k_max), np.inf, np.float32)
+    st = np.zeros((len(Q), 4), np.int64)
+    for k, ef in sorted(set(zip(ks.tolist(), efs.tolist()))):
+        sel = np.nonzero((ks == k) & (efs == ef))[0]
+        oi, od, os_ = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], Q[sel], k, ef, with_stats=True)
+        ids[sel, :k], d[sel, :k], st[sel] = oi, od, os_
+    return ids, d, st
+
+
+@pytest.mark.parametrize("seed,nq", [(0, 200), (1, 37), (2, 1)])
+def test_mixed_batch_equals_oracle_per_query(cfg1, seed, nq):
+    c = cfg1
+    rng = np.random.default_rng(seed)
+    Q = np.concatenate([c["Q"], c["Q"] + 0.05])[:nq] if nq <= 400 else None
+    ks = rng.choice([1, 3, 10, 17, 64], nq).astype(np.int32)
+    efs = rng.choice([1, 4, 16, 40, 96, 200], nq).astype(np.int32)
+    k_max, ef_max = 64, 256
+    print(f"mixed seed={seed} nq={nq}", flush=True)
+    ids, d, st = c["idx"].search_mixed(T(Q), T(ks), T(efs), k_max, ef_max, stats=True)
+    torch.cuda.synchronize()
+    oi, od, os_ = _oracle_rows(c, Q, ks, efs, k_max)
+    gi, gd, gs = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    bad = np.nonzero((gi != oi).any(axis=1))[0]
+    assert bad.size == 0, f"ids differ for queries {bad[:10].tolist()}"
+    assert np.array_equal(gd, od)
+    assert np.array_equal(gs[:, :3], os_[:, :3])
+
+
+def test_mixed_uniform_equals_plain_search(cfg1):
+    c = cfg1
+    Qd = T(c["Q"])
+    nq = Qd.shape[0]
+    ids, d, st = c["idx"].search(Qd, 10, 64, stats=True)
+    k = torch.full((nq,), 10, dtype=torch.int32, device=DEV)
+    ef = torch.full((nq,), 64, dtype=torch.int32, device=DEV)
+    mi, md, ms = c["idx"].search_mixed(Qd, k, ef, stats=True)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, mi) and torch.equal(d, md) and torch.equal(st, ms)
+
+
+def test_mixed_rejects_out_of_range_rows(cfg1):
+    c = cfg1
+    Q = c["Q"][:6]
+    ks = np.array([10, 0, 10, 65, 5, -3], np.int32)
+    efs = np.array([32, 32, 0, 32, 300, 32], np.int32)
+    ids, d, st = c["idx"].search_mixed(T(Q), T(ks), T(efs), 64, 256, stats=True)
+    torch.cuda.synchronize()
+    gi, gd, gs = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    for q in (1, 2, 3, 4, 5):
+        assert (gi[q] == -1).all() and np.isinf(gd[q]).all() and gs[q].tolist() == [0, 0, 0, -1]
+    oi, od = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], Q[:1], 10, 32)
+    assert np.array_equal(gi[0, :10], oi[0]) and (gi[0, 10:] == -1).all() and gs[0, 3] == 0
+
+
+def test_mixed_argument_errors(cfg1):
+    idx = cfg1["idx"]
+    Qd = T(cfg1["Q"][:4])
+    k = torch.full((4,), 10, dtype=torch.int32, device=DEV)
+    with pytest.raises(qg.QGError):
+        idx.search_mixed(Qd, k, k, 10, qg.QG_MAX_EF + 1)
+    with pytest.raises(qg.QGError):
+        idx.search_mixed(Qd, k, k, 0, 10)
+
+
+def test_graph_capture_replays_equal_eager(cfg1):
+    """qg_search and qg_search_mixed recorded into HIP graphs (through torch's
+    capture on the library's stream): three replays with other device work
+    between them each equal the eager results."""
+    c = cfg1
+    idx = c["idx"]
+    Qd = T(c["Q"])
+    nq = Qd.shape[0]
+    ks = T(np.resize(np.array([1, 10, 30], np.int32), nq))
+    efs = T(np.resize(np.array([64, 16, 128, 40], np.int32), nq))
+    ref = idx.search(Qd, 10, 64, stats=True)
+    refm = idx.search_mixed(Qd, ks, efs, 30, 128, stats=True)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        idx.search(Qd, 10, 64)  # warm-up on the capture stream
+    idx.reserve(nq)  # the scratch the graph will refer to exists before capture
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        idx.set_stream(torch.cuda.current_stream())
+        out = idx.search(Qd, 10, 64, stats=True)
+        outm = idx.search_mixed(Qd, ks, efs, 30, 128, stats=True)
+    idx.set_stream(None)
+    torch.cuda.synchronize()
+    print("graph captured", flush=True)
+    other = T(c["Q"][::-1].copy())
+    for rep in range(3):
+        idx.search(other, 5, 32)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), f"replay {rep}: uniform search differs"
+        for a, b in zip(outm, refm):
+            assert torch.equal(a, b), f"replay {rep}: mixed search differs"
