@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--load-index", default="", help="search a saved index (no recall: ground truth is not rebuilt)")
     ap.add_argument("--no-learned-stop", action="store_true", help="time only the fixed-ef search")
     ap.add_argument("--ls-ef", type=int, default=0, help="beam size for the learned stop (default: the fixed ef)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shape with qg_autotune on the benchmark queries before timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -162,6 +164,12 @@ def main():
         with torch.cuda.stream(stream):
             idx.search(Qs, k, ef)
 
+    tuned = None
+    if args.autotune:
+        with torch.cuda.stream(stream):
+            wpb, hf, tms = idx.autotune(Qs, k, ef)
+        tuned = {"waves_per_workgroup": wpb, "hash_factor": hf, "best_call_ms": round(tms, 4)}
+        log(f"[bench] autotune: {tuned}")
     qps, ms_per_step, kern_ms, rot_ms = timed(plain)
     expansions = int(s[:, 0].sum())
     alg_bytes = expansions * idx.block_bytes + args.nq * (4 * D + 8 * k)
@@ -171,7 +179,7 @@ def main():
                 "bytes_per_launch": alg_bytes, "expansions_per_launch": expansions,
                 "block_bytes": idx.block_bytes, "kernel_ms": round(kern_ms, 4), "rotate_kernel_ms": round(rot_ms, 4)}
     fixed = {"ef": ef, "recall@10": round(rec, 4), "qps": round(qps, 1), "ms_per_step": round(ms_per_step, 4),
-             "mean_expansions": round(expansions / args.nq, 2)}
+             "mean_expansions": round(expansions / args.nq, 2), "autotune": tuned}
 
     # learned stop: trained on separately seeded queries, theta picked on a held-out part of them
     ls_res = None

@@ -155,6 +155,18 @@ int qg_copy_blocks(const qg_index *idx, int64_t first, int64_t count, void *dst)
  * must not overlap in time on different streams. */
 int qg_set_stream(qg_index *idx, void *hip_stream);
 
+/* Launch-shape autotuning.  Times qg_search_ex on the given device queries
+ * (k, ef, flags as they will be used) for every combination of wavefronts per
+ * workgroup (1, 2, 4, 8; halved at launch while the LDS does not fit) and
+ * visited-hash size (2^h >= F * ef slots, F = 2, 3, 4; a smaller table leaves
+ * room for more wavefronts, a larger one sends fewer queries to the overflow
+ * pass) and keeps the fastest for later searches of this index.  Results do
+ * not depend on the choice, only the speed.  Outputs (host, nullable): the
+ * chosen wavefronts per workgroup and F, and the best time in ms of one
+ * qg_search_ex call.  Synchronous; allocates and frees temporary outputs. */
+int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                int32_t *out_wpb, int32_t *out_hash_factor, double *out_ms);
+
 /* Grow the index's per-query scratch (rotated queries, overflow list) to hold
  * at least nq queries.  Searches grow it themselves (reallocating) when a
  * batch is larger than any before; captured graphs refer to the scratch that

@@ -76,6 +76,10 @@ struct qg_index {
   uint32_t* fb_bits = nullptr;
   int fb_slots = 0;
   int64_t fb_words = 0;
+  // launch shape chosen by qg_autotune: wavefronts per workgroup (preferred,
+  // halved while the LDS does not fit) and visited-hash slots per beam entry
+  int wpb_pref = 4;
+  int hash_factor = 3;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev[2];  // pairs per kernel class
@@ -404,7 +408,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   // visited hash: 2^h >= 3 ef slots (at least 256), filled to at most one half;
   // queries that visit more finish in the overflow pass
   int hbits = 8;
-  while ((1 << hbits) < 3 * ef && hbits < 14) ++hbits;
+  while ((1 << hbits) < idx->hash_factor * ef && hbits < 14) ++hbits;
   if (flags & QG_SEARCH_SMALL_HASH) hbits = 7;
   qgk::SearchArgs a{};
   a.blocks = idx->blocks;
@@ -430,8 +434,8 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   a.overflow_list = idx->overflow;
   a.fb_bits = idx->fb_bits;
   a.fb_words = idx->fb_words;
-  // ls_mode 1: stop only, MLP in LDS; 2: trace (and the MLP, if given, read from global memory)
-  const int ls = !stop ? 0 : (stop->trace_max == 0 && stop->mlp ? 1 : 2);
+  // ls_mode 1: stop only, MLP in LDS; 2: trace (and the MLP, if given, read from global memory); 3: mixed batch
+  const int ls = ef_q ? 3 : !stop ? 0 : (stop->trace_max == 0 && stop->mlp ? 1 : 2);
   if (stop) {
     a.ls_w = stop->mlp;
     a.ls_theta = stop->theta;
@@ -448,7 +452,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
   const size_t lds_cap = 160 * 1024;
   const size_t extra = ls == 1 ? qgk::mlp_lds_bytes() : 0;  // MLP image shared by a workgroup
-  int wpb = 4;
+  int wpb = idx->wpb_pref;
   while (wpb > 1 && (size_t)wpb * L.total + extra > lds_cap) wpb >>= 1;
   if ((size_t)L.total + extra > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
   const size_t lds = (size_t)wpb * L.total + extra;
@@ -481,6 +485,64 @@ int qg_search_mixed(const qg_index* idx, const float* queries, int64_t nq, const
   if (nq > 0 && (!k_per_query || !ef_per_query)) return fail(QG_EINVAL, "NULL per-query k or ef array");
   return search_impl(idx, queries, nq, k_max, ef_max, k_per_query, ef_per_query, flags, nullptr, out_ids, out_dists,
                      out_stats);
+}
+
+int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                int32_t* out_wpb, int32_t* out_hash_factor, double* out_ms) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (nq <= 0 || !queries) return fail(QG_EINVAL, "autotuning needs queries");
+  DeviceGuard g(idx->device);
+  int32_t* ids = nullptr;
+  float* dists = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const int keep_wpb = idx->wpb_pref, keep_hf = idx->hash_factor;
+  int best_wpb = keep_wpb, best_hf = keep_hf, rc = QG_OK;
+  double best = -1.0;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(ids);
+    (void)hipFree(dists);
+  };
+  if (hipMalloc(&ids, sizeof(int32_t) * (size_t)(nq * k)) != hipSuccess ||
+      hipMalloc(&dists, sizeof(float) * (size_t)(nq * k)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(QG_ENOMEM, "autotune buffers");
+  }
+  for (int wpb : {1, 2, 4, 8}) {
+    for (int hf : {2, 3, 4}) {
+      idx->wpb_pref = wpb;
+      idx->hash_factor = hf;
+      // one untimed call, then the best of three timed ones
+      if ((rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr))) break;
+      double t = -1.0;
+      for (int rep = 0; rep < 3 && rc == QG_OK; ++rep) {
+        float ms = 0.0f;
+        if (hipEventRecord(e0, idx->stream) != hipSuccess) rc = fail(QG_EDEVICE, "hipEventRecord");
+        if (!rc) rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr);
+        if (!rc && (hipEventRecord(e1, idx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = fail(QG_EDEVICE, "timing events");
+        if (!rc && (t < 0 || ms < t)) t = ms;
+      }
+      if (rc) break;
+      if (best < 0 || t < best) {
+        best = t;
+        best_wpb = wpb;
+        best_hf = hf;
+      }
+    }
+    if (rc) break;
+  }
+  cleanup();
+  idx->wpb_pref = rc ? keep_wpb : best_wpb;
+  idx->hash_factor = rc ? keep_hf : best_hf;
+  if (rc) return rc;
+  if (out_wpb) *out_wpb = best_wpb;
+  if (out_hash_factor) *out_hash_factor = best_hf;
+  if (out_ms) *out_ms = best;
+  return QG_OK;
 }
 
 int qg_reserve(qg_index* idx, int64_t nq) {

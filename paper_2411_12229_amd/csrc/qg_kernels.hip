@@ -478,7 +478,12 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 // of w3[j] * h2[j] plus the output bias.  Parameter layout: W1[64][16], b1[64],
 // W2[64][64], b2[64], W3[64], b3.
 // learned-stop modes of the search kernels
-constexpr int kLsOff = 0, kLsStop = 1, kLsTrace = 2;
+// Kernel modes: plain search, learned stop (MLP in LDS), learned stop with
+// trace, and per-query k / ef (a mixed batch).  Each is its own instantiation,
+// so the plain kernel carries none of the others' state.
+constexpr int kLsOff = 0, kLsStop = 1, kLsTrace = 2, kMixed = 3;
+template <int LS>
+constexpr bool has_stop = LS == kLsStop || LS == kLsTrace;
 
 constexpr int kLsW1 = 0, kLsB1 = 64 * 16, kLsW2 = kLsB1 + 64, kLsB2 = kLsW2 + 64 * 64, kLsW3 = kLsB2 + 64,
               kLsB3 = kLsW3 + 64;
@@ -613,7 +618,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   constexpr uint64_t kNone = ~0ull;  // sorts after every real entry
   const int lane = lane_id();
   int ef = a.ef, k = a.k;
-  if (a.ef_q) {
+  if constexpr (LS == kMixed) {
     // a beam size and result count of its own; a.ef and a.k are the bounds
     ef = uni(a.ef_q[q]);
     k = uni(a.k_q[q]);
@@ -770,14 +775,14 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       best = ((uint64_t)hk << 32) | lo;
     }
     // o2f (and o2u, for the stop features) beyond the popped chunk
-    if (!o2f_known || (LS != kLsOff && !o2u_known)) {
-      for (int base = cursor; base < size && !(o2f_known && (LS == kLsOff || o2u_known)); base += 64) {
+    if (!o2f_known || (has_stop<LS> && !o2u_known)) {
+      for (int base = cursor; base < size && !(o2f_known && (!has_stop<LS> || o2u_known)); base += 64) {
         const int i = base + lane;
         const uint64_t e = (i < size) ? beam[i] : (uint64_t)kChecked;
         const bool un = !((uint32_t)e & kChecked);
         const uint64_t mu = ballot(un);
         if (!mu) continue;
-        if (LS != kLsOff && !o2u_known) {
+        if (has_stop<LS> && !o2u_known) {
           o2u = rdlane64(e, first_lane(mu));
           o2u_known = true;
         }
@@ -935,7 +940,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       size = (size + nv < ef) ? size + nv : ef;
     }
 
-    if constexpr (LS != kLsOff) {
+    if constexpr (has_stop<LS>) {
       if (expansions >= a.ls_t_min && (expansions - a.ls_t_min) % a.ls_t_every == 0) {
         StopFeatures F;
         const float nn1 = uni(nkey[0]), nnk = uni(nkey[nnc - 1]);
@@ -963,9 +968,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   }
 
   // answer: NN ascending by (distance, id), padded with (-1, inf)
-  for (int i = lane; i < a.k_out; i += 64) {  // k_out = k, or the row stride of a mixed batch
-    a.out_ids[q * a.k_out + i] = i < nnc ? (int32_t)nid[i] : -1;
-    a.out_dists[q * a.k_out + i] = i < nnc ? nkey[i] : __builtin_inff();
+  const int k_out = LS == kMixed ? a.k_out : k;  // a mixed batch's rows are k_out wide
+  for (int i = lane; i < k_out; i += 64) {
+    a.out_ids[q * k_out + i] = i < nnc ? (int32_t)nid[i] : -1;
+    a.out_dists[q * k_out + i] = i < nnc ? nkey[i] : __builtin_inff();
   }
   if (a.out_stats && lane == 0) {
     int32_t* st = a.out_stats + 4 * q;
@@ -981,7 +987,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // GV = true : overflow pass over the queries the main pass handed over, with
 //             a global bitset per wavefront.
 template <int D, int R, bool GV, int LS>
-__global__ __launch_bounds__(256) void search_kernel(SearchArgs a) {
+__global__ __launch_bounds__(512) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
   const int lane = lane_id();
@@ -1094,6 +1100,7 @@ hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const Se
     case kLsOff: return launch_search_t<d, r, gv, kLsOff>(a, grid, wpb, lds, st);     \
     case kLsStop: return launch_search_t<d, r, gv, kLsStop>(a, grid, wpb, lds, st);   \
     case kLsTrace: return launch_search_t<d, r, gv, kLsTrace>(a, grid, wpb, lds, st); \
+    case kMixed: return launch_search_t<d, r, gv, kMixed>(a, grid, wpb, lds, st);     \
     default: return hipErrorInvalidValue;                                           \
   }
 #define QG_CASE(d, r)                  \
@@ -1113,6 +1120,7 @@ int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, siz
     case kLsOff: return occupancy_t<d, r, gv, kLsOff>(wpb, lds);            \
     case kLsStop: return occupancy_t<d, r, gv, kLsStop>(wpb, lds);          \
     case kLsTrace: return occupancy_t<d, r, gv, kLsTrace>(wpb, lds);        \
+    case kMixed: return occupancy_t<d, r, gv, kMixed>(wpb, lds);            \
     default: return 0;                                                    \
   }
 #define QG_CASE(d, r)                  \

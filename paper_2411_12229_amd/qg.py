@@ -59,6 +59,8 @@ def _load():
         "qg_copy_blocks": ([P, i64, i64, P], c_int),
         "qg_set_stream": ([P, P], c_int),
         "qg_reserve": ([P, i64], c_int),
+        "qg_autotune": ([P, P, i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                         ctypes.POINTER(ctypes.c_double)], c_int),
         "qg_index_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)], c_int),
         "qg_timing": ([P, c_int], c_int),
@@ -119,6 +121,14 @@ class Index:
         """Run later work on a torch.cuda.Stream (None = null stream)."""
         self._stream = stream
         _check(_lib.qg_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)))
+
+    def autotune(self, queries: torch.Tensor, k: int, ef: int, flags: int = 0):
+        """Pick the launch shape (wavefronts per workgroup, visited-hash factor) by timing searches of
+        these queries; returns (wpb, hash_factor, best ms per call)."""
+        w, h, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.qg_autotune(self._h, _dev(queries, torch.float32, "queries"), queries.shape[0], k, ef, flags,
+                                ctypes.byref(w), ctypes.byref(h), ctypes.byref(ms)))
+        return w.value, h.value, ms.value
 
     def reserve(self, nq: int) -> None:
         """Size the query scratch for batches of up to nq queries (before capturing graphs)."""

@@ -40,4 +40,5 @@ def test_error_paths_without_device():
     assert lib.qg_search(None, None, 0, 10, 10, None, None) == -1
     assert lib.qg_search_mixed(None, None, ctypes.c_int64(4), None, None, 10, 10, 0, None, None, None) == -1
     assert lib.qg_reserve(None, ctypes.c_int64(10)) == -1
+    assert lib.qg_autotune(None, None, ctypes.c_int64(0), 10, 10, 0, None, None, None) == -1
     lib.qg_free_index(None)

@@ -142,3 +142,22 @@ def test_graph_capture_replays_equal_eager(cfg1):
             assert torch.equal(a, b), f"replay {rep}: uniform search differs"
         for a, b in zip(outm, refm):
             assert torch.equal(a, b), f"replay {rep}: mixed search differs"
+
+
+@pytest.mark.parametrize("k,ef", [(10, 512), (10, 64)])
+def test_autotune_keeps_results(cfg1, k, ef):
+    """The tuner only changes the launch shape: results before and after are
+    bit-identical (and equal the oracle's)."""
+    c = cfg1
+    idx = c["idx"]
+    Qd = T(c["Q"])
+    before = idx.search(Qd, k, ef, stats=True)
+    wpb, hf, ms = idx.autotune(Qd, k, ef)
+    print(f"autotune k={k} ef={ef}: wpb={wpb} hash factor={hf} {ms:.3f} ms", flush=True)
+    assert wpb in (1, 2, 4, 8) and hf in (2, 3, 4) and ms > 0
+    after = idx.search(Qd, k, ef, stats=True)
+    torch.cuda.synchronize()
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)
+    oi, od = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], k, ef)
+    assert np.array_equal(after[0].cpu().numpy(), oi) and np.array_equal(after[1].cpu().numpy(), od)
