@@ -167,6 +167,51 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
 int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                 int32_t *out_wpb, int32_t *out_hash_factor, double *out_ms);
 
+/* ---- Serving loop (continuous batching) ----------------------------------
+ * A server owns `streams` slots over one index.  Each slot has its own
+ * stream, its own view of the index (the blocks are shared, the search
+ * scratch is not) and pinned staging buffers for max_batch queries.  A worker
+ * thread takes every waiting request (up to max_batch) as soon as a slot is
+ * free and runs upload, one qg_search_mixed launch and download on that
+ * slot's stream, so batches grow with the load and the slots overlap
+ * transfers with searches.  Every request's results are those of qg_search_ex
+ * for that query alone with its own k and ef.  The index must outlive the
+ * server; 1 <= streams <= 16, 1 <= k_max <= QG_MAX_K, 1 <= ef_max <= QG_MAX_EF. */
+typedef struct qg_server qg_server;
+
+int qg_server_create(qg_index *idx, int32_t streams, int32_t max_batch, int32_t k_max, int32_t ef_max,
+                     qg_server **out);
+
+/* Queue one request: query[d] (fp32, host memory, copied before the call
+ * returns), 1 <= k <= k_max, 1 <= ef <= ef_max, and a caller tag returned with
+ * the results.  Thread-safe; never blocks on the device. */
+int qg_server_submit(qg_server *s, const float *query, int32_t k, int32_t ef, uint64_t tag);
+
+/* Move up to max_results finished requests out of the server, oldest first.
+ * Host outputs, each nullable: tags[n], ids[n][k_max] and dists[n][k_max]
+ * (a request's k results, then (-1, +inf)), latency_s[n] (submission to
+ * completion seen by the worker, seconds).  Returns the number written, or a
+ * negative QG_* code. */
+int64_t qg_server_poll(qg_server *s, int64_t max_results, uint64_t *tags, int32_t *ids, float *dists,
+                       double *latency_s);
+
+/* Submit queries[n][d] (host) with tags 0 .. n-1 at arrival_s[i] seconds after
+ * the call (an open-loop arrival trace), from a thread of the server; returns
+ * at once.  The arrays must stay valid until qg_server_drain returns. */
+int qg_server_replay(qg_server *s, const float *queries, const int32_t *k, const int32_t *ef,
+                     const double *arrival_s, int64_t n);
+
+/* Wait until every submitted request has finished (its results wait for
+ * poll), at most timeout_s seconds.  Ends a running replay first. */
+int qg_server_drain(qg_server *s, double timeout_s);
+
+/* Counters (host, nullable): requests submitted and finished, batches
+ * launched and the largest batch. */
+int qg_server_stats(qg_server *s, int64_t *submitted, int64_t *completed, int64_t *batches, int64_t *largest_batch);
+
+/* Finish every queued request, stop the worker and free the server. */
+void qg_server_destroy(qg_server *s);
+
 /* Grow the index's per-query scratch (rotated queries, overflow list) to hold
  * at least nq queries.  Searches grow it themselves (reallocating) when a
  * batch is larger than any before; captured graphs refer to the scratch that

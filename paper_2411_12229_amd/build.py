@@ -9,8 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqg.so")
-SOURCES = [os.path.join(CSRC, "qg_kernels.hip"), os.path.join(CSRC, "qg_api.cpp")]
-HEADERS = [os.path.join(CSRC, "qg_kernels.h"), os.path.join(CSRC, "qg_layout.h"),
+SOURCES = [os.path.join(CSRC, "qg_kernels.hip"), os.path.join(CSRC, "qg_api.cpp"), os.path.join(CSRC, "qg_server.cpp")]
+HEADERS = [os.path.join(CSRC, "qg_kernels.h"), os.path.join(CSRC, "qg_layout.h"), os.path.join(CSRC, "qg_internal.h"),
            os.path.join(ROOT, "include", "qg.h")]
 
 FLAGS = [

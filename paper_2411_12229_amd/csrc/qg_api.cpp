@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "qg.h"
+#include "qg_internal.h"
 #include "qg_kernels.h"
 #include "qg_layout.h"
 
@@ -60,6 +61,7 @@ class DeviceGuard {
 }  // namespace
 
 struct qg_index {
+  bool owns_data = true;  // false for a view: rot and blocks belong to another handle
   int device = 0;
   hipStream_t stream = nullptr;
   int64_t N = 0;
@@ -108,8 +110,10 @@ static int alloc_common(qg_index* idx) {
 static void release(qg_index* idx) {
   if (!idx) return;
   DeviceGuard g(idx->device);
-  (void)hipFree(idx->rot);
-  (void)hipFree(idx->blocks);
+  if (idx->owns_data) {
+    (void)hipFree(idx->rot);
+    (void)hipFree(idx->blocks);
+  }
   (void)hipFree(idx->qrot);
   (void)hipFree(idx->overflow);
   (void)hipFree(idx->counters);
@@ -162,6 +166,48 @@ static int record(qg_index* idx, int kind, bool start) {
 extern "C" {
 
 const char* qg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+namespace qgi {
+
+qg_index* make_view(const qg_index* base) {
+  if (!base) {
+    fail(QG_EINVAL, "index is NULL");
+    return nullptr;
+  }
+  DeviceGuard g(base->device);
+  qg_index* v = new qg_index;
+  v->owns_data = false;
+  v->device = base->device;
+  v->N = base->N;
+  v->D = base->D;
+  v->R = base->R;
+  v->entry = base->entry;
+  v->block_bytes = base->block_bytes;
+  v->rot = base->rot;
+  v->blocks = base->blocks;
+  v->wpb_pref = base->wpb_pref;
+  v->hash_factor = base->hash_factor;
+  v->fb_slots = base->fb_slots;
+  v->fb_words = base->fb_words;
+  if (hipMalloc(&v->counters, sizeof(int) * kCounters) != hipSuccess ||
+      hipMemset(v->counters, 0, sizeof(int) * kCounters) != hipSuccess ||
+      hipMalloc(&v->fb_bits, sizeof(uint32_t) * (size_t)(v->fb_words * v->fb_slots)) != hipSuccess) {
+    release(v);
+    fail(QG_ENOMEM, "index view scratch");
+    return nullptr;
+  }
+  return v;
+}
+
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+int device_of(const qg_index* idx) { return idx->device; }
+int dim_of(const qg_index* idx) { return idx->D; }
+
+}  // namespace qgi
+
+extern "C" {
 
 void qg_free_index(qg_index* idx) { release(idx); }
 

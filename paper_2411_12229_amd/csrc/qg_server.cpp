@@ -1,0 +1,382 @@
+// qg_server.cpp -- a serving loop over one index (C ABI in include/qg.h).
+//
+// Requests (one query, its k and ef, a caller tag) are queued by any thread.
+// One worker thread owns S stream slots; each slot has its own view of the
+// index (shared blocks, private scratch) and pinned staging buffers.  Whenever
+// a slot is free the worker takes every waiting request (up to the batch
+// limit) and enqueues on that slot's stream: the queries' upload, one mixed
+// search launch (a k and ef per query) and the results' download, then an
+// event.  Batches therefore grow with the load and shrink when it is light
+// (continuous batching), and the S slots overlap transfers with searches.
+// Latency is measured on the host from submission to the moment the worker
+// sees the batch's event complete.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "qg.h"
+#include "qg_internal.h"
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  uint64_t tag = 0;
+  int32_t k = 0, ef = 0;
+  double t_submit = 0;
+  std::vector<float> q;
+};
+
+struct Result {
+  uint64_t tag = 0;
+  int32_t k = 0;
+  double latency = 0;
+  std::vector<int32_t> ids;
+  std::vector<float> dists;
+};
+
+struct Slot {
+  qg_index* view = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  float* h_q = nullptr;  // pinned host staging
+  int32_t* h_k = nullptr;
+  int32_t* h_ef = nullptr;
+  int32_t* h_ids = nullptr;
+  float* h_dists = nullptr;
+  float* d_q = nullptr;  // device
+  int32_t* d_k = nullptr;
+  int32_t* d_ef = nullptr;
+  int32_t* d_ids = nullptr;
+  float* d_dists = nullptr;
+  std::vector<Request> batch;
+  bool busy = false;
+};
+
+}  // namespace
+
+struct qg_server {
+  qg_index* idx = nullptr;
+  int device = 0, D = 0;
+  int32_t k_max = 0, ef_max = 0, max_batch = 0;
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv;  // new requests, or a stop request, for the idle worker
+  std::condition_variable cv_done;  // completions, for drain
+  std::deque<Request> pending;
+  std::deque<Result> done;
+  int64_t submitted = 0, completed = 0, batches = 0, largest = 0;
+  int error = QG_OK;
+  std::string errmsg;
+  bool stop = false;
+  std::thread worker;
+  std::thread producer;
+};
+
+namespace {
+
+void free_slot(Slot& s) {
+  (void)hipFree(s.d_q);
+  (void)hipFree(s.d_k);
+  (void)hipFree(s.d_ef);
+  (void)hipFree(s.d_ids);
+  (void)hipFree(s.d_dists);
+  (void)hipHostFree(s.h_q);
+  (void)hipHostFree(s.h_k);
+  (void)hipHostFree(s.h_ef);
+  (void)hipHostFree(s.h_ids);
+  (void)hipHostFree(s.h_dists);
+  if (s.done) (void)hipEventDestroy(s.done);
+  if (s.view) qg_free_index(s.view);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  s = Slot{};
+}
+
+bool init_slot(qg_server* sv, Slot& s) {
+  const size_t B = (size_t)sv->max_batch, K = (size_t)sv->k_max, D = (size_t)sv->D;
+  if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
+  if (hipHostMalloc(&s.h_q, sizeof(float) * B * D) != hipSuccess ||
+      hipHostMalloc(&s.h_k, sizeof(int32_t) * B) != hipSuccess ||
+      hipHostMalloc(&s.h_ef, sizeof(int32_t) * B) != hipSuccess ||
+      hipHostMalloc(&s.h_ids, sizeof(int32_t) * B * K) != hipSuccess ||
+      hipHostMalloc(&s.h_dists, sizeof(float) * B * K) != hipSuccess)
+    return false;
+  if (hipMalloc(&s.d_q, sizeof(float) * B * D) != hipSuccess || hipMalloc(&s.d_k, sizeof(int32_t) * B) != hipSuccess ||
+      hipMalloc(&s.d_ef, sizeof(int32_t) * B) != hipSuccess ||
+      hipMalloc(&s.d_ids, sizeof(int32_t) * B * K) != hipSuccess ||
+      hipMalloc(&s.d_dists, sizeof(float) * B * K) != hipSuccess)
+    return false;
+  s.view = qgi::make_view(sv->idx);
+  if (!s.view) return false;
+  if (qg_set_stream(s.view, s.stream) != QG_OK || qg_reserve(s.view, sv->max_batch) != QG_OK) return false;
+  return true;
+}
+
+void fail_server(qg_server* sv, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->error == QG_OK) {
+    sv->error = QG_EDEVICE;
+    sv->errmsg = msg;
+  }
+  sv->cv_done.notify_all();
+}
+
+// Enqueue one batch on a free slot.  Returns false on a device error.
+bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
+  const int n = (int)take.size();
+  const size_t D = (size_t)sv->D;
+  for (int i = 0; i < n; ++i) {
+    std::memcpy(s.h_q + (size_t)i * D, take[i].q.data(), sizeof(float) * D);
+    s.h_k[i] = take[i].k;
+    s.h_ef[i] = take[i].ef;
+  }
+  const size_t K = (size_t)sv->k_max;
+  if (hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * D * n, hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+      hipMemcpyAsync(s.d_k, s.h_k, sizeof(int32_t) * n, hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+      hipMemcpyAsync(s.d_ef, s.h_ef, sizeof(int32_t) * n, hipMemcpyHostToDevice, s.stream) != hipSuccess) {
+    fail_server(sv, "upload of a batch failed");
+    return false;
+  }
+  if (qg_search_mixed(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, sv->ef_max, 0, s.d_ids, s.d_dists, nullptr) !=
+      QG_OK) {
+    fail_server(sv, std::string("search: ") + qg_last_error());
+    return false;
+  }
+  if (hipMemcpyAsync(s.h_ids, s.d_ids, sizeof(int32_t) * K * n, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+      hipMemcpyAsync(s.h_dists, s.d_dists, sizeof(float) * K * n, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+      hipEventRecord(s.done, s.stream) != hipSuccess) {
+    fail_server(sv, "download of a batch failed");
+    return false;
+  }
+  s.batch = std::move(take);
+  s.busy = true;
+  return true;
+}
+
+void worker_loop(qg_server* sv) {
+  (void)hipSetDevice(sv->device);
+  const size_t K = (size_t)sv->k_max;
+  for (;;) {
+    bool progressed = false, any_busy = false;
+    // completions
+    for (auto& s : sv->slots) {
+      if (!s.busy) continue;
+      const hipError_t e = hipEventQuery(s.done);
+      if (e == hipErrorNotReady) {
+        any_busy = true;
+        continue;
+      }
+      if (e != hipSuccess) {
+        fail_server(sv, std::string("batch failed: ") + hipGetErrorString(e));
+        s.busy = false;
+        continue;
+      }
+      const double t = now_s();
+      std::lock_guard<std::mutex> lk(sv->mu);
+      for (size_t i = 0; i < s.batch.size(); ++i) {
+        Result r;
+        r.tag = s.batch[i].tag;
+        r.k = s.batch[i].k;
+        r.latency = t - s.batch[i].t_submit;
+        r.ids.assign(s.h_ids + i * K, s.h_ids + i * K + r.k);
+        r.dists.assign(s.h_dists + i * K, s.h_dists + i * K + r.k);
+        sv->done.push_back(std::move(r));
+      }
+      sv->completed += (int64_t)s.batch.size();
+      s.batch.clear();
+      s.busy = false;
+      progressed = true;
+      sv->cv_done.notify_all();
+    }
+    // dispatch whatever waits onto a free slot
+    for (auto& s : sv->slots) {
+      if (s.busy) continue;
+      std::vector<Request> take;
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->error != QG_OK) break;
+        const size_t n = std::min(sv->pending.size(), (size_t)sv->max_batch);
+        for (size_t i = 0; i < n; ++i) {
+          take.push_back(std::move(sv->pending.front()));
+          sv->pending.pop_front();
+        }
+        if (n) {
+          ++sv->batches;
+          sv->largest = std::max<int64_t>(sv->largest, (int64_t)n);
+        }
+      }
+      if (take.empty()) break;
+      if (!dispatch(sv, s, std::move(take))) break;
+      any_busy = progressed = true;
+    }
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (sv->stop && sv->pending.empty() && !any_busy) break;
+    if (sv->error != QG_OK && !any_busy) {
+      // a failed server completes nothing more: drop what waits
+      sv->pending.clear();
+      if (sv->stop) break;
+    }
+    if (!progressed) {
+      if (any_busy) {
+        lk.unlock();
+        std::this_thread::yield();  // a batch is in flight: poll its event again soon
+      } else if (sv->pending.empty() && !sv->stop) {
+        sv->cv.wait_for(lk, std::chrono::milliseconds(50));
+      }
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int qg_server_create(qg_index* idx, int32_t streams, int32_t max_batch, int32_t k_max, int32_t ef_max,
+                     qg_server** out) {
+  if (!out) return qgi::set_error(QG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!idx) return qgi::set_error(QG_EINVAL, "index is NULL");
+  if (streams < 1 || streams > 16) return qgi::set_error(QG_EINVAL, "streams must be in [1, 16]");
+  if (max_batch < 1 || max_batch > (1 << 20)) return qgi::set_error(QG_EINVAL, "max_batch must be in [1, 2^20]");
+  if (k_max < 1 || k_max > QG_MAX_K || ef_max < 1 || ef_max > QG_MAX_EF)
+    return qgi::set_error(QG_EINVAL, "k_max or ef_max out of range");
+  qg_server* sv = new qg_server;
+  sv->idx = idx;
+  sv->device = qgi::device_of(idx);
+  sv->D = qgi::dim_of(idx);
+  sv->k_max = k_max;
+  sv->ef_max = ef_max;
+  sv->max_batch = max_batch;
+  int old = 0;
+  (void)hipGetDevice(&old);
+  (void)hipSetDevice(sv->device);
+  sv->slots.resize(streams);
+  bool ok = true;
+  for (auto& s : sv->slots) ok = ok && init_slot(sv, s);
+  (void)hipSetDevice(old);
+  if (!ok) {
+    for (auto& s : sv->slots) free_slot(s);
+    delete sv;
+    return qgi::set_error(QG_ENOMEM, "server buffers or streams");
+  }
+  sv->worker = std::thread(worker_loop, sv);
+  *out = sv;
+  return QG_OK;
+}
+
+int qg_server_submit(qg_server* sv, const float* query, int32_t k, int32_t ef, uint64_t tag) {
+  if (!sv || !query) return qgi::set_error(QG_EINVAL, "server or query is NULL");
+  if (k < 1 || k > sv->k_max || ef < 1 || ef > sv->ef_max)
+    return qgi::set_error(QG_EINVAL, "k or ef outside the server's bounds");
+  Request r;
+  r.tag = tag;
+  r.k = k;
+  r.ef = ef;
+  r.q.assign(query, query + sv->D);
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->error != QG_OK) return qgi::set_error(sv->error, sv->errmsg);
+    if (sv->stop) return qgi::set_error(QG_EINVAL, "server is stopping");
+    r.t_submit = now_s();
+    sv->pending.push_back(std::move(r));
+    ++sv->submitted;
+  }
+  sv->cv.notify_one();
+  return QG_OK;
+}
+
+int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32_t* ids, float* dists,
+                       double* latency_s) {
+  if (!sv || max_results < 0) return qgi::set_error(QG_EINVAL, "server is NULL or max_results < 0");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  const int64_t n = std::min<int64_t>(max_results, (int64_t)sv->done.size());
+  const size_t K = (size_t)sv->k_max;
+  for (int64_t i = 0; i < n; ++i) {
+    const Result& r = sv->done.front();
+    if (tags) tags[i] = r.tag;
+    if (latency_s) latency_s[i] = r.latency;
+    for (size_t j = 0; j < K; ++j) {
+      const bool in = j < (size_t)r.k;
+      if (ids) ids[i * K + j] = in ? r.ids[j] : -1;
+      if (dists) dists[i * K + j] = in ? r.dists[j] : __builtin_inff();
+    }
+    sv->done.pop_front();
+  }
+  return n;
+}
+
+int qg_server_replay(qg_server* sv, const float* queries, const int32_t* k, const int32_t* ef,
+                     const double* arrival_s, int64_t n) {
+  if (!sv || n < 0 || (n > 0 && (!queries || !k || !ef || !arrival_s)))
+    return qgi::set_error(QG_EINVAL, "bad replay arguments");
+  if (sv->producer.joinable()) return qgi::set_error(QG_EINVAL, "a replay is already running");
+  for (int64_t i = 0; i < n; ++i)
+    if (k[i] < 1 || k[i] > sv->k_max || ef[i] < 1 || ef[i] > sv->ef_max)
+      return qgi::set_error(QG_EINVAL, "k or ef outside the server's bounds");
+  sv->producer = std::thread([sv, queries, k, ef, arrival_s, n]() {
+    const double t0 = now_s();
+    for (int64_t i = 0; i < n; ++i) {
+      while (now_s() - t0 < arrival_s[i]) {
+      }  // open loop: request i enters at its arrival time
+      if (qg_server_submit(sv, queries + (size_t)i * sv->D, k[i], ef[i], (uint64_t)i) != QG_OK) break;
+    }
+  });
+  return QG_OK;
+}
+
+int qg_server_drain(qg_server* sv, double timeout_s) {
+  if (!sv) return qgi::set_error(QG_EINVAL, "server is NULL");
+  if (sv->producer.joinable()) sv->producer.join();
+  std::unique_lock<std::mutex> lk(sv->mu);
+  const auto until = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+  while (sv->completed < sv->submitted && sv->error == QG_OK) {
+    if (sv->cv_done.wait_until(lk, until) == std::cv_status::timeout) return qgi::set_error(QG_EINVAL, "drain timed out");
+  }
+  if (sv->error != QG_OK) return qgi::set_error(sv->error, sv->errmsg);
+  return QG_OK;
+}
+
+int qg_server_stats(qg_server* sv, int64_t* submitted, int64_t* completed, int64_t* batches, int64_t* largest_batch) {
+  if (!sv) return qgi::set_error(QG_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (submitted) *submitted = sv->submitted;
+  if (completed) *completed = sv->completed;
+  if (batches) *batches = sv->batches;
+  if (largest_batch) *largest_batch = sv->largest;
+  return QG_OK;
+}
+
+void qg_server_destroy(qg_server* sv) {
+  if (!sv) return;
+  if (sv->producer.joinable()) sv->producer.join();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  int old = 0;
+  (void)hipGetDevice(&old);
+  (void)hipSetDevice(sv->device);
+  for (auto& s : sv->slots) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    free_slot(s);
+  }
+  (void)hipSetDevice(old);
+  delete sv;
+}
+
+}  // extern "C"

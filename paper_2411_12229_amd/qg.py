@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,6 +67,14 @@ def _load():
         "qg_timing": ([P, c_int], c_int),
         "qg_timing_read": ([P, c_int, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
         "qg_free_index": ([P], None),
+        "qg_server_create": ([P, i32, i32, i32, i32, PP], c_int),
+        "qg_server_submit": ([P, P, i32, i32, ctypes.c_uint64], c_int),
+        "qg_server_poll": ([P, i64, P, P, P, P], i64),
+        "qg_server_replay": ([P, P, P, P, P, i64], c_int),
+        "qg_server_drain": ([P, ctypes.c_double], c_int),
+        "qg_server_stats": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+                            c_int),
+        "qg_server_destroy": ([P], None),
         "qg_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -340,3 +349,74 @@ def qg_timing_read(idx: Index, kernel: int):
 
 def qg_free_index(idx: Index) -> None:
     idx.free()
+
+
+def _host(a: np.ndarray, dtype, name: str):
+    if not isinstance(a, np.ndarray) or a.dtype != dtype or not a.flags.c_contiguous:
+        raise TypeError(f"{name} must be a C-contiguous numpy array of {np.dtype(dtype).name}")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Server:
+    """The library's serving loop over one index (qg_server_*): requests with
+    their own k and ef are batched continuously onto `streams` device streams."""
+
+    def __init__(self, index: Index, streams: int = 2, max_batch: int = 1024, k_max: int = 100, ef_max: int = 256):
+        h = ctypes.c_void_p()
+        _check(_lib.qg_server_create(index.handle, streams, max_batch, k_max, ef_max, ctypes.byref(h)))
+        self._h, self._index, self.d, self.k_max = h, index, index.d, k_max
+        self._replay = None
+
+    def submit(self, query: np.ndarray, k: int, ef: int, tag: int) -> None:
+        q = np.ascontiguousarray(query, dtype=np.float32).reshape(-1)
+        if q.shape[0] != self.d:
+            raise ValueError("query has the wrong dimension")
+        _check(_lib.qg_server_submit(self._h, ctypes.c_void_p(q.ctypes.data), k, ef, ctypes.c_uint64(tag)))
+
+    def poll(self, max_results: int = 1 << 16, payload: bool = True):
+        """-> (tags uint64 [n], ids int32 [n,k_max], dists f32 [n,k_max], latency s [n]) of finished requests."""
+        tags = np.empty(max_results, np.uint64)
+        lat = np.empty(max_results, np.float64)
+        ids = np.empty((max_results, self.k_max), np.int32) if payload else None
+        dists = np.empty((max_results, self.k_max), np.float32) if payload else None
+        n = _lib.qg_server_poll(self._h, max_results, ctypes.c_void_p(tags.ctypes.data),
+                                ctypes.c_void_p(ids.ctypes.data) if payload else None,
+                                ctypes.c_void_p(dists.ctypes.data) if payload else None,
+                                ctypes.c_void_p(lat.ctypes.data))
+        if n < 0:
+            _check(int(n))
+        return tags[:n], (ids[:n] if payload else None), (dists[:n] if payload else None), lat[:n]
+
+    def replay(self, queries: np.ndarray, k: np.ndarray, ef: np.ndarray, arrival_s: np.ndarray) -> None:
+        """Submit an open-loop trace (request i at arrival_s[i] seconds, tag i) from a library thread."""
+        arrs = (np.ascontiguousarray(queries, dtype=np.float32), np.ascontiguousarray(k, dtype=np.int32),
+                np.ascontiguousarray(ef, dtype=np.int32), np.ascontiguousarray(arrival_s, dtype=np.float64))
+        n = arrs[0].shape[0]
+        if arrs[0].shape != (n, self.d) or arrs[1].shape != (n,) or arrs[2].shape != (n,) or arrs[3].shape != (n,):
+            raise ValueError("trace shape mismatch")
+        self._replay = arrs  # kept alive until drain
+        _check(_lib.qg_server_replay(self._h, _host(arrs[0], np.float32, "queries"), _host(arrs[1], np.int32, "k"),
+                                     _host(arrs[2], np.int32, "ef"), _host(arrs[3], np.float64, "arrival_s"), n))
+
+    def drain(self, timeout_s: float = 120.0) -> None:
+        try:
+            _check(_lib.qg_server_drain(self._h, float(timeout_s)))
+        finally:
+            self._replay = None
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(_lib.qg_server_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("submitted", "completed", "batches", "largest_batch"), (x.value for x in v)))
+
+    def close(self) -> None:
+        if self._h:
+            _lib.qg_server_destroy(self._h)
+            self._h = None
+            self._replay = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

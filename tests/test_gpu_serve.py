@@ -1,0 +1,129 @@
+"""The serving loop (qg_server_*, through the C ABI): requests with their own
+k and ef, batched continuously onto several streams.
+
+Bar: every request's result equals the result of searching that query alone
+with its own k and ef (ids and distances bit-equal, which the oracle also
+returns); every tag comes back exactly once; a timed open-loop trace reports
+sane latencies.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2411_12229_amd import qg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    X, Q = synth.gen_data(1)
+    M = synth.rotation(128, synth.seed(1, "rotation"))
+    G = synth.knn_graph(X, 32, synth.seed(1, "long"))
+    e = synth.medoid(X)
+    blocks = oracle.encode(X, G, M)
+    print("cfg1 index: N=10000 D=128 R=32", flush=True)
+    idx = qg.qg_build_index(T(X), T(G), T(M), e)
+    return dict(X=X, Q=Q, M=M, G=G, e=e, blocks=blocks, idx=idx)
+
+
+def _alone(c, Q, ks, efs, k_max):
+    """Each query searched by itself on the device (plain qg_search_ex) and by the oracle."""
+    ids = np.full((len(Q), k_max), -1, np.int32)
+    d = np.full((len(Q), k_max), np.inf, np.float32)
+    for i in range(len(Q)):
+        gi, gd = c["idx"].search(T(Q[i:i + 1]), int(ks[i]), int(efs[i]))
+        ids[i, :ks[i]], d[i, :ks[i]] = gi.cpu().numpy()[0], gd.cpu().numpy()[0]
+    for k, ef in set(zip(ks.tolist(), efs.tolist())):
+        sel = np.nonzero((ks == k) & (efs == ef))[0]
+        oi, od = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], Q[sel], k, ef)
+        assert np.array_equal(ids[sel, :k], oi) and np.array_equal(d[sel, :k], od)
+    return ids, d
+
+
+def _collect(srv, n):
+    tags, ids, dists, lat = [], [], [], []
+    while sum(len(t) for t in tags) < n:
+        t, i, d, l = srv.poll()
+        tags.append(t), ids.append(i), dists.append(d), lat.append(l)
+    return np.concatenate(tags), np.concatenate(ids), np.concatenate(dists), np.concatenate(lat)
+
+
+def test_each_result_alone_equals_in_the_mix(cfg1):
+    c = cfg1
+    rng = np.random.default_rng(5)
+    Q = np.concatenate([c["Q"], c["Q"] + 0.03]).astype(np.float32)
+    n = len(Q)
+    ks = rng.choice([1, 10, 100], n).astype(np.int32)
+    efs = rng.choice([16, 64, 200], n).astype(np.int32)
+    srv = qg.Server(c["idx"], streams=3, max_batch=64, k_max=100, ef_max=256)
+    try:
+        order = rng.permutation(n)
+        for i in order:
+            srv.submit(Q[i], int(ks[i]), int(efs[i]), int(i))
+        srv.drain()
+        tags, ids, dists, lat = _collect(srv, n)
+        st = srv.stats()
+    finally:
+        srv.close()
+    print(f"served {n} requests in {st['batches']} batches (largest {st['largest_batch']})", flush=True)
+    assert sorted(tags.tolist()) == list(range(n))
+    assert st["submitted"] == st["completed"] == n and 1 <= st["largest_batch"] <= 64
+    ref_ids, ref_d = _alone(c, Q, ks, efs, 100)
+    assert np.array_equal(ids, ref_ids[tags]) and np.array_equal(dists, ref_d[tags])
+    assert (lat > 0).all()
+
+
+def test_replay_open_loop_trace(cfg1):
+    c = cfg1
+    rng = np.random.default_rng(9)
+    n = 4000
+    Q = c["Q"][rng.integers(0, len(c["Q"]), n)].astype(np.float32)
+    ks = rng.choice([1, 10], n).astype(np.int32)
+    efs = rng.choice([32, 96], n).astype(np.int32)
+    arrival = np.cumsum(rng.exponential(1.0 / 50_000, n))  # Poisson, 50k requests/s
+    srv = qg.Server(c["idx"], streams=2, max_batch=512, k_max=10, ef_max=96)
+    try:
+        srv.replay(Q, ks, efs, arrival)
+        srv.drain()
+        tags, ids, dists, lat = _collect(srv, n)
+        st = srv.stats()
+    finally:
+        srv.close()
+    p50, p99 = np.percentile(lat, [50, 99])
+    print(f"replay 50k/s: p50 {p50 * 1e6:.0f} us, p99 {p99 * 1e6:.0f} us, {st['batches']} batches", flush=True)
+    assert sorted(tags.tolist()) == list(range(n))
+    assert 0 < p50 <= p99 < 1.0
+    for k, ef in ((1, 32), (10, 96)):
+        sel = np.nonzero((ks[tags] == k) & (efs[tags] == ef))[0]
+        gi, gd = c["idx"].search(T(Q[tags[sel]]), k, ef)
+        assert np.array_equal(ids[sel, :k], gi.cpu().numpy()) and np.array_equal(dists[sel, :k], gd.cpu().numpy())
+
+
+def test_server_argument_errors(cfg1):
+    with pytest.raises(qg.QGError):
+        qg.Server(cfg1["idx"], streams=0)
+    srv = qg.Server(cfg1["idx"], streams=1, max_batch=8, k_max=10, ef_max=64)
+    try:
+        with pytest.raises(qg.QGError):
+            srv.submit(cfg1["Q"][0], 11, 32, 0)
+        with pytest.raises(qg.QGError):
+            srv.submit(cfg1["Q"][0], 5, 65, 0)
+        srv.submit(cfg1["Q"][0], 5, 64, 7)
+        srv.drain()
+        tags, ids, _, _ = _collect(srv, 1)
+        assert tags.tolist() == [7] and (ids[0, 5:] == -1).all()
+    finally:
+        srv.close()
