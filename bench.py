@@ -51,6 +51,7 @@ def main():
     ap.add_argument("--ls-ef", type=int, default=0, help="beam size for the learned stop (default: the fixed ef)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with qg_autotune on the benchmark queries before timing")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -298,6 +299,43 @@ def main():
     e2e_qps = args.nq * args.steps / (time.perf_counter() - t1)
     log(f"[bench] end to end with PCIe copies: {e2e_qps:,.0f} q/s")
 
+    # serving loop (continuous batching): open-loop Poisson traces of single
+    # queries with k ~ U{1, 10, 100} and ef ~ U{ef/2, ef, 4 ef}
+    serving = None
+    if not args.no_serve:
+        serving = []
+        rng = np.random.default_rng(11)
+        ef_classes = (max(ef // 2, 1), ef, 4 * ef)
+        for rate in (200_000, 1_000_000, 4_000_000):
+            n = int(min(rate * 0.4, 400_000))
+            qsel = rng.integers(0, args.nq, n)
+            ks = rng.choice([1, 10, 100], n).astype(np.int32)
+            efs = rng.choice(ef_classes, n).astype(np.int32)
+            arrival = np.cumsum(rng.exponential(1.0 / rate, n))
+            srv = qg.Server(idx, streams=3, max_batch=8192, k_max=100, ef_max=max(ef_classes))
+            try:
+                t0 = time.perf_counter()
+                srv.replay(Q[qsel], ks, efs, arrival)
+                got, lat = 0, []
+                while got < n:
+                    t, _, _, l = srv.poll(1 << 18, payload=False)
+                    got += len(t)
+                    lat.append(l)
+                    if not len(t):
+                        time.sleep(0.001)
+                wall = time.perf_counter() - t0
+                srv.drain()
+                st = srv.stats()
+            finally:
+                srv.close()
+            lat = np.concatenate(lat)
+            p50, p99 = np.percentile(lat, [50, 99])
+            row = {"offered_per_s": rate, "requests": n, "completed_per_s": round(n / wall, 1),
+                   "p50_ms": round(p50 * 1e3, 3), "p99_ms": round(p99 * 1e3, 3), "batches": st["batches"],
+                   "mean_batch": round(n / max(st["batches"], 1), 1), "largest_batch": st["largest_batch"]}
+            serving.append(row)
+            log(f"[bench] serving {rate:,}/s offered: {row}")
+
     cpu = None
     if not args.no_cpu and X is not None:
         sys.path.insert(0, os.path.join(ROOT, "oracle"))
@@ -352,6 +390,9 @@ def main():
         "fixed_ef": fixed,
         "learned_stop": ls_res,
         "end_to_end_qps_with_pcie": round(e2e_qps, 1),
+        "serving": {"workload": f"single queries from the {args.nq} benchmark queries, open-loop Poisson arrivals, "
+                                f"k ~ U{{1,10,100}}, ef ~ U{{{max(ef // 2, 1)},{ef},{4 * ef}}}, 3 streams, "
+                                "batches up to 8192", "rates": serving} if serving is not None else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,
