@@ -498,7 +498,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
   const size_t lds_cap = 160 * 1024;
   const size_t extra = ls == 1 ? qgk::mlp_lds_bytes() : 0;  // MLP image shared by a workgroup
-  int wpb = idx->wpb_pref;
+  int wpb = ls == 1 ? 8 : idx->wpb_pref;  // stop-only: 8 wavefronts share the MLP image
   while (wpb > 1 && (size_t)wpb * L.total + extra > lds_cap) wpb >>= 1;
   if ((size_t)L.total + extra > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
   const size_t lds = (size_t)wpb * L.total + extra;

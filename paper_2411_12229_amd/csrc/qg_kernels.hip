@@ -357,6 +357,10 @@ struct BlockView {
   static constexpr int DPL = (D + 63) / 64; // raw dims per lane
   static constexpr bool WORDS = (BPL % 4) == 0;
   static constexpr int NW = WORDS ? BPL / 4 : BPL / 2;  // 32- or 16-bit code units per lane
+  // Whether a second block (the next vertex, prefetched) is held in registers
+  // beside this one (every shape built here: at most 45 words per lane);
+  // wider shapes would load the block when it is used instead.
+  static constexpr bool kRegPrefetch = NW + DPL <= 48;
   float x[DPL];
   uint32_t cw[NW];
   float fa, fr;
@@ -398,6 +402,14 @@ struct BlockView {
       // each lookup address is the base plus one byte of a register
       const uint32_t ev = (cw[w] << 1) & 0x1E1E1E1Eu, od = (cw[w] >> 3) & 0x1E1E1E1Eu;
       s += lut_sum<0, UNIT_NIB>(b8 + w * UNIT_NIB * 32, ev, od);
+      // wide codes: keep the lookups of one unit together, so that not all of
+      // them are in flight (and in registers) at once
+      if constexpr (NW > 4) {
+        // the running sum passes through here: this unit's lookups are summed
+        // (and their registers free) before the next unit's are issued
+        asm volatile("" : "+v"(s)::"memory");
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     if constexpr (LPN == 2) s += xor_lane_i<1>(s);
     return s;
@@ -574,31 +586,45 @@ __device__ __forceinline__ void stage_mlp(const uint16_t* __restrict__ w, uint8_
     m16[t] = t < 64 ? w[kLsB1 + t] : w[kLsB2 + (t - 64)];  // b2, W3 and b3 are contiguous
 }
 
-__device__ __forceinline__ float stop_mlp_lds(const uint8_t* m, float f, int lane) {
+// bc: 256 bytes of this wavefront's LDS free during the evaluation; the
+// features and then the first hidden layer pass through it, so every lane
+// reads them back four at a time (broadcast reads) instead of one readlane each.
+__device__ __forceinline__ float stop_mlp_lds(const uint8_t* m, float f, int lane, float* bc) {
   const uint4* W = reinterpret_cast<const uint4*>(m);
   const uint16_t* m16 = reinterpret_cast<const uint16_t*>(m + kMlpB1);
+  if (lane < 16) bc[lane] = f;
+  wave_sync();
   float acc = __uint_as_float((uint32_t)m16[lane] << 16);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const uint4 v = W[c * 64 + lane];
-    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      acc = __builtin_fmaf(bf16lo(u[h]), rdlane(f, 8 * c + 2 * h), acc);
-      acc = __builtin_fmaf(bf16hi(u[h]), rdlane(f, 8 * c + 2 * h + 1), acc);
-    }
+    const float4 x0 = reinterpret_cast<const float4*>(bc)[2 * c], x1 = reinterpret_cast<const float4*>(bc)[2 * c + 1];
+    acc = __builtin_fmaf(bf16lo(v.x), x0.x, acc);
+    acc = __builtin_fmaf(bf16hi(v.x), x0.y, acc);
+    acc = __builtin_fmaf(bf16lo(v.y), x0.z, acc);
+    acc = __builtin_fmaf(bf16hi(v.y), x0.w, acc);
+    acc = __builtin_fmaf(bf16lo(v.z), x1.x, acc);
+    acc = __builtin_fmaf(bf16hi(v.z), x1.y, acc);
+    acc = __builtin_fmaf(bf16lo(v.w), x1.z, acc);
+    acc = __builtin_fmaf(bf16hi(v.w), x1.w, acc);
   }
   const float h1 = acc > 0.0f ? acc : 0.0f;
+  wave_sync();
+  bc[lane] = h1;  // the features have been read
+  wave_sync();
   acc = __uint_as_float((uint32_t)m16[64 + lane] << 16);
-#pragma unroll 2
+#pragma unroll 1
   for (int c = 0; c < 8; ++c) {
     const uint4 v = W[(2 + c) * 64 + lane];
-    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      acc = __builtin_fmaf(bf16lo(u[h]), rdlane(h1, 8 * c + 2 * h), acc);
-      acc = __builtin_fmaf(bf16hi(u[h]), rdlane(h1, 8 * c + 2 * h + 1), acc);
-    }
+    const float4 x0 = reinterpret_cast<const float4*>(bc)[2 * c], x1 = reinterpret_cast<const float4*>(bc)[2 * c + 1];
+    acc = __builtin_fmaf(bf16lo(v.x), x0.x, acc);
+    acc = __builtin_fmaf(bf16hi(v.x), x0.y, acc);
+    acc = __builtin_fmaf(bf16lo(v.y), x0.z, acc);
+    acc = __builtin_fmaf(bf16hi(v.y), x0.w, acc);
+    acc = __builtin_fmaf(bf16lo(v.z), x1.x, acc);
+    acc = __builtin_fmaf(bf16hi(v.z), x1.y, acc);
+    acc = __builtin_fmaf(bf16lo(v.w), x1.z, acc);
+    acc = __builtin_fmaf(bf16hi(v.w), x1.w, acc);
   }
   const float h2 = acc > 0.0f ? acc : 0.0f;
   const float pr = __uint_as_float((uint32_t)m16[128 + lane] << 16) * h2;
@@ -653,13 +679,35 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     for (int i = lane; i < (1 << a.hash_bits); i += 64) vis.tab[i] = kEmpty;
   }
 
-  float qv[DPL];
+  // the raw query: in registers, or for the wide shapes (D > 256) in LDS,
+  // read back dim by dim (same arithmetic either way)
+  constexpr bool kQvLds = qgl::query_in_lds(D);
+  float qv[kQvLds ? 1 : DPL];
+  float* qs = reinterpret_cast<float*>(lds + L.qv);
   const float* qr = a.queries + q * D;
+  if constexpr (kQvLds) {
+    static_assert(D % 64 == 0, "wide shapes have D a multiple of 64");
+    for (int i = lane; i < D; i += 64) qs[i] = qr[i];
+  } else {
 #pragma unroll
-  for (int t = 0; t < DPL; ++t) {
-    const int i = lane + 64 * t;
-    qv[t] = (i < D) ? qr[i] : 0.0f;
+    for (int t = 0; t < DPL; ++t) {
+      const int i = lane + 64 * t;
+      qv[t] = (i < D) ? qr[i] : 0.0f;
+    }
   }
+  auto dist = [&](const float(&xv)[DPL]) {
+    if constexpr (kQvLds) {
+      float p = 0.0f;
+#pragma unroll
+      for (int t = 0; t < DPL; ++t) {
+        const float d = qs[lane + 64 * t] - xv[t];
+        p = __builtin_fmaf(d, d, p);
+      }
+      return butterfly_f(p);
+    } else {
+      return exact_dist<DPL>(qv, xv);
+    }
+  };
   const float delta = build_lut<D, R>(a.qrot + q * D, lut);
 
   // S starts with the entry keyed by its exact distance (reading S13).
@@ -667,7 +715,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   {
     BV e;
     e.load(a.blocks + (int64_t)a.entry * a.block_bytes, lane);
-    de = uni(exact_dist<DPL>(qv, e.x));
+    de = uni(dist(e.x));
   }
   uint64_t tail = pack_kv(de, (uint32_t)a.entry);  // beam[ef - 1] whenever the beam is full
   beam[0] = tail;
@@ -750,7 +798,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     else
       b.load(a.blocks + (int64_t)p * a.block_bytes, lane);
     nxt_id = kEmpty;
-    const float dp = uni(exact_dist<DPL>(qv, b.x));
+    const float dp = uni(dist(b.x));
 
     // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
     const int S = b.fastscan(lut, lane);
@@ -804,8 +852,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const uint64_t nxt_f = best < o2f ? best : o2f;
     if (nxt_f != kNone) {
       const uint32_t nx = (uint32_t)nxt_f & kIdMask;
-      nxt.load(a.blocks + (int64_t)nx * a.block_bytes, lane);
-      nxt_id = nx;
+      if constexpr (BV::kRegPrefetch) {
+        nxt.load(a.blocks + (int64_t)nx * a.block_bytes, lane);
+        nxt_id = nx;
+      }
     }
 
     // implicit re-ranking: NN keeps the k smallest (distance, id) seen
@@ -947,7 +997,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         F.compute(expansions, pops, nnc, k, since, de, nn1, nnk, bfk, size, ef, dp, app, R);
         float out;
         if constexpr (LS == kLsStop)
-          out = stop_mlp_lds(mlp, F.mine, lane);
+          out = stop_mlp_lds(mlp, F.mine, lane, reinterpret_cast<float*>(lds + L.cand));
         else
           out = a.ls_w ? stop_mlp(a.ls_w, F, lane) : __builtin_nanf("");
         if constexpr (LS == kLsTrace) {
@@ -986,8 +1036,12 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // GV = false: main pass over all queries with the LDS visited hash.
 // GV = true : overflow pass over the queries the main pass handed over, with
 //             a global bitset per wavefront.
+// The stop-only kernels share one MLP image per workgroup of 8 wavefronts;
+// for the narrow shapes their registers are held to 80 so that LDS, not
+// registers, sets residency (6 wavefronts per SIMD).
 template <int D, int R, bool GV, int LS>
-__global__ __launch_bounds__(512) void search_kernel(SearchArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LS == kLsStop && D <= 256 ? 6 : 1))) void search_kernel(
+    SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
   const int lane = lane_id();
