@@ -155,6 +155,29 @@ def test_search_parity_shapes(D, R, cfg):
         gpu = _search(idx, Q, k, ef)
         orc = oracle.search(blocks, D, R, e, M, Q, k, ef, with_stats=True)
         _assert_same(gpu, orc, f"D={D} R={R} k={k} ef={ef}")
+    # the per-query (mixed batch) kernel on the same shape
+    ks = np.resize(np.array([10, 100, 1], np.int32), len(Q))
+    efs = np.resize(np.array([32, 128, 64], np.int32), len(Q))
+    mi, md, ms = idx.search_mixed(T(Q), T(ks), T(efs), 100, 128, stats=True)
+    torch.cuda.synchronize()
+    mi, md, ms = mi.cpu().numpy(), md.cpu().numpy(), ms.cpu().numpy()
+    for k, ef in ((10, 32), (100, 128), (1, 64)):
+        sel = np.nonzero((ks == k) & (efs == ef))[0]
+        oi, od, os_ = oracle.search(blocks, D, R, e, M, Q[sel], k, ef, with_stats=True)
+        _assert_same((mi[sel, :k], md[sel, :k], ms[sel]), (oi, od, os_), f"mixed D={D} R={R} k={k} ef={ef}")
+        assert (mi[sel, k:] == -1).all()
+    # the learned-stop kernel (MLP in LDS) on the same shape, theta set so that some queries stop
+    rng = np.random.default_rng(D + R)
+    w = ((rng.standard_normal(oracle.LS_PARAMS) * 0.3).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    _, _, _, (_, _, oo, oc) = oracle.search_ls(blocks, D, R, e, M, Q, 10, 64, w=w, theta=np.inf, t_min=4, t_every=2,
+                                               max_evals=128)
+    outs = np.concatenate([oo[i, :oc[i]] for i in range(len(oc))])
+    theta = float(np.quantile(outs, 0.7))
+    si, sd, ss, _ = idx.search_stop(T(Q), 10, 64, torch.from_numpy(w.view(np.int16)).to(DEV), theta=theta, t_min=4,
+                                    t_every=2, stats=True)
+    torch.cuda.synchronize()
+    oi, od, os_, _ = oracle.search_ls(blocks, D, R, e, M, Q, 10, 64, w=w, theta=theta, t_min=4, t_every=2)
+    _assert_same((si.cpu().numpy(), sd.cpu().numpy(), ss.cpu().numpy()), (oi, od, os_), f"stop D={D} R={R}")
 
 
 def test_search_parity_algorithm2_graph():
