@@ -190,17 +190,44 @@ def main():
         _, Qtr = synth.gen_data(2, n=1, nq=20_000, qseed=synth.seed(2, "train"))
         gt_tr, _ = synth.ground_truth(X, Qtr, k, device=dev)
         Qtr_d, gt_tr_d = torch.from_numpy(Qtr).to(dev), torch.from_numpy(gt_tr).to(dev)
-        ls_ef = args.ls_ef or ef
-        t_min, t_every = 8, 4
+        t_min = 8
+        # beam sizes tried: the fixed-ef winner and the next swept size (a larger
+        # beam lets hard queries run on while the stop ends easy ones early)
+        ls_efs = (args.ls_ef,) if args.ls_ef else tuple(e for e in (ef, next((x for x in EFS if x > ef), ef))
+                                                         if e <= 128) or (ef,)
+        Qth, gt_th = Qtr_d[16_000:].contiguous(), gt_tr_d[16_000:]
+        best_ls = None
+        feat_points = 0
         with torch.cuda.stream(stream):
-            feat, lab = learned_stop.collect(idx, Qtr_d[:16_000].contiguous(), gt_tr_d[:16_000], k, ls_ef, t_min,
-                                             t_every)
-            model = learned_stop.train(feat, lab, epochs=6)
-            bits = learned_stop.export(model)
-            pick = learned_stop.pick_theta(idx, Qtr_d[16_000:].contiguous(), gt_tr_d[16_000:], bits, k, ls_ef,
-                                           t_min, t_every, target=args.target + 0.005)
-        stream.synchronize()
-        log(f"[bench] learned stop: {feat.shape[0]} trace points, trained in {time.time() - t0:.1f}s, theta {pick}")
+            for ls_ef_c in dict.fromkeys(ls_efs):
+                feat, lab = learned_stop.collect(idx, Qtr_d[:16_000].contiguous(), gt_tr_d[:16_000], k, ls_ef_c,
+                                                 t_min, 4)
+                feat_points += int(feat.shape[0])
+                model = learned_stop.train(feat, lab, epochs=6)
+                bits_c = learned_stop.export(model)
+                # evaluation every 4 or every 8 expansions (the points of the second are
+                # a subset of the first): theta for each on the held-out queries, then
+                # the fastest setting on those queries
+                for te in (4, 8):
+                    got = learned_stop.pick_theta(idx, Qth, gt_th, bits_c, k, ls_ef_c, t_min, te,
+                                                  target=args.target + 0.005)
+                    if got is None:
+                        continue
+                    idx.search_stop(Qth, k, ls_ef_c, bits_c, theta=got[0], t_min=t_min, t_every=te)
+                    stream.synchronize()
+                    idx.timing(True)
+                    for _ in range(5):
+                        idx.search_stop(Qth, k, ls_ef_c, bits_c, theta=got[0], t_min=t_min, t_every=te)
+                    stream.synchronize()
+                    idx.timing(False)
+                    nl, tms = idx.timing_read(1)
+                    log(f"[bench] learned stop ef={ls_ef_c} t_every={te}: theta {got[0]}, held-out recall "
+                        f"{got[1]:.4f}, {tms / nl:.4f} ms per 4000 queries")
+                    if best_ls is None or tms / nl < best_ls[0]:
+                        best_ls = (tms / nl, te, got, ls_ef_c, bits_c)
+        pick = best_ls[2] if best_ls is not None else None
+        if best_ls is not None:
+            t_every, ls_ef, bits = best_ls[1], best_ls[3], best_ls[4]
         if pick is not None:
             theta = pick[0]
             with torch.cuda.stream(stream):
@@ -217,7 +244,7 @@ def main():
             qps_l, ms_l, kern_l, _ = timed(stopped)
             ls_res = {"ef": ls_ef, "theta": theta, "t_min": t_min, "t_every": t_every, "recall@10": round(rec_l, 4),
                       "qps": round(qps_l, 1), "ms_per_step": round(ms_l, 4), "kernel_ms": round(kern_l, 4),
-                      "mean_expansions": round(exp_l / args.nq, 2), "trace_points": int(feat.shape[0]),
+                      "mean_expansions": round(exp_l / args.nq, 2), "trace_points": feat_points,
                       "train_queries": 16_000, "theta_queries": 4_000}
             log(f"[bench] learned stop ef={ls_ef} theta={theta}: recall@10={rec_l:.4f} {qps_l:,.0f} q/s "
                 f"(fixed ef={ef}: recall {rec:.4f} {qps:,.0f} q/s)")

@@ -170,11 +170,13 @@ int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int3
 /* ---- Serving loop (continuous batching) ----------------------------------
  * A server owns `streams` slots over one index.  Each slot has its own
  * stream, its own view of the index (the blocks are shared, the search
- * scratch is not) and pinned staging buffers for max_batch queries.  A worker
- * thread takes every waiting request (up to max_batch) as soon as a slot is
- * free and runs upload, one qg_search_mixed launch and download on that
- * slot's stream, so batches grow with the load and the slots overlap
- * transfers with searches.  Every request's results are those of qg_search_ex
+ * scratch is not) and pinned staging buffers for max_batch queries.  Requests
+ * wait in classes of beam size (ef up to a power of two).  As soon as a slot
+ * is free, a worker thread takes the class of the oldest waiting request and
+ * every waiting request of that class (up to max_batch), and runs upload, one
+ * qg_search_mixed launch sized for the batch's largest ef, and download on
+ * that slot's stream.  Batches grow with the load, short searches never wait
+ * in a batch for long ones, and the slots overlap transfers with searches.  Every request's results are those of qg_search_ex
  * for that query alone with its own k and ef.  The index must outlive the
  * server; 1 <= streams <= 16, 1 <= k_max <= QG_MAX_K, 1 <= ef_max <= QG_MAX_EF. */
 typedef struct qg_server qg_server;

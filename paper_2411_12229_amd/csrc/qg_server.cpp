@@ -1,13 +1,16 @@
 // qg_server.cpp -- a serving loop over one index (C ABI in include/qg.h).
 //
-// Requests (one query, its k and ef, a caller tag) are queued by any thread.
-// One worker thread owns S stream slots; each slot has its own view of the
-// index (shared blocks, private scratch) and pinned staging buffers.  Whenever
-// a slot is free the worker takes every waiting request (up to the batch
-// limit) and enqueues on that slot's stream: the queries' upload, one mixed
-// search launch (a k and ef per query) and the results' download, then an
-// event.  Batches therefore grow with the load and shrink when it is light
-// (continuous batching), and the S slots overlap transfers with searches.
+// Requests (one query, its k and ef, a caller tag) are queued by any thread,
+// in classes of beam size (ef up to 2^c).  One worker thread owns S stream
+// slots; each slot has its own view of the index (shared blocks, private
+// scratch) and pinned staging buffers.  Whenever a slot is free the worker
+// takes the class of the oldest waiting request, every waiting request of that
+// class (up to the batch limit), and enqueues on that slot's stream: the
+// queries' upload, one mixed search launch sized for the batch's largest ef
+// (a k and ef per query) and the results' download, then an event.  Batches
+// grow with the load and shrink when it is light (continuous batching); a
+// batch of short searches never waits for a long one and is sized for its own
+// beam (more wavefronts fit), and the S slots overlap transfers with searches.
 // Latency is measured on the host from submission to the moment the worker
 // sees the batch's event complete.
 #include <hip/hip_runtime.h>
@@ -39,12 +42,14 @@ struct Request {
   std::vector<float> q;
 };
 
-struct Result {
-  uint64_t tag = 0;
-  int32_t k = 0;
-  double latency = 0;
-  std::vector<int32_t> ids;
-  std::vector<float> dists;
+// One finished batch: its rows are handed out by poll, oldest first.
+struct DoneBatch {
+  std::vector<uint64_t> tags;
+  std::vector<int32_t> ks;
+  std::vector<double> latency;
+  std::vector<int32_t> ids;  // [n][k_max]
+  std::vector<float> dists;  // [n][k_max]
+  size_t next = 0;           // rows already polled
 };
 
 struct Slot {
@@ -75,8 +80,10 @@ struct qg_server {
   std::mutex mu;
   std::condition_variable cv;  // new requests, or a stop request, for the idle worker
   std::condition_variable cv_done;  // completions, for drain
-  std::deque<Request> pending;
-  std::deque<Result> done;
+  static constexpr int kClasses = 12;  // ef <= 2^c, c < 12 (QG_MAX_EF = 2^11)
+  std::deque<Request> pending[kClasses];
+  int64_t npending = 0;
+  std::deque<DoneBatch> done;
   int64_t submitted = 0, completed = 0, batches = 0, largest = 0;
   int error = QG_OK;
   std::string errmsg;
@@ -134,6 +141,12 @@ void fail_server(qg_server* sv, const std::string& msg) {
   sv->cv_done.notify_all();
 }
 
+int ef_class(int32_t ef) {
+  int c = 0;
+  while ((1 << c) < ef) ++c;
+  return c;
+}
+
 // Enqueue one batch on a free slot.  Returns false on a device error.
 bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
   const int n = (int)take.size();
@@ -150,7 +163,9 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
     fail_server(sv, "upload of a batch failed");
     return false;
   }
-  if (qg_search_mixed(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, sv->ef_max, 0, s.d_ids, s.d_dists, nullptr) !=
+  int32_t ef_batch = 1;
+  for (int i = 0; i < n; ++i) ef_batch = std::max(ef_batch, take[i].ef);
+  if (qg_search_mixed(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, ef_batch, 0, s.d_ids, s.d_dists, nullptr) !=
       QG_OK) {
     fail_server(sv, std::string("search: ") + qg_last_error());
     return false;
@@ -185,20 +200,26 @@ void worker_loop(qg_server* sv) {
         continue;
       }
       const double t = now_s();
-      std::lock_guard<std::mutex> lk(sv->mu);
-      for (size_t i = 0; i < s.batch.size(); ++i) {
-        Result r;
-        r.tag = s.batch[i].tag;
-        r.k = s.batch[i].k;
-        r.latency = t - s.batch[i].t_submit;
-        r.ids.assign(s.h_ids + i * K, s.h_ids + i * K + r.k);
-        r.dists.assign(s.h_dists + i * K, s.h_dists + i * K + r.k);
-        sv->done.push_back(std::move(r));
+      const size_t n = s.batch.size();
+      DoneBatch db;  // built outside the lock: one record per batch
+      db.tags.resize(n);
+      db.ks.resize(n);
+      db.latency.resize(n);
+      for (size_t i = 0; i < n; ++i) {
+        db.tags[i] = s.batch[i].tag;
+        db.ks[i] = s.batch[i].k;
+        db.latency[i] = t - s.batch[i].t_submit;
       }
-      sv->completed += (int64_t)s.batch.size();
+      db.ids.assign(s.h_ids, s.h_ids + n * K);
+      db.dists.assign(s.h_dists, s.h_dists + n * K);
       s.batch.clear();
       s.busy = false;
       progressed = true;
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->done.push_back(std::move(db));
+        sv->completed += (int64_t)n;
+      }
       sv->cv_done.notify_all();
     }
     // dispatch whatever waits onto a free slot
@@ -208,11 +229,19 @@ void worker_loop(qg_server* sv) {
       {
         std::lock_guard<std::mutex> lk(sv->mu);
         if (sv->error != QG_OK) break;
-        const size_t n = std::min(sv->pending.size(), (size_t)sv->max_batch);
-        for (size_t i = 0; i < n; ++i) {
-          take.push_back(std::move(sv->pending.front()));
-          sv->pending.pop_front();
+        int c = -1;  // the class of the oldest waiting request
+        for (int i = 0; i < qg_server::kClasses; ++i)
+          if (!sv->pending[i].empty() && (c < 0 || sv->pending[i].front().t_submit < sv->pending[c].front().t_submit))
+            c = i;
+        if (c >= 0) {
+          auto& q = sv->pending[c];
+          while (!q.empty() && (int)take.size() < sv->max_batch) {
+            take.push_back(std::move(q.front()));
+            q.pop_front();
+          }
         }
+        const size_t n = take.size();
+        sv->npending -= (int64_t)n;
         if (n) {
           ++sv->batches;
           sv->largest = std::max<int64_t>(sv->largest, (int64_t)n);
@@ -223,17 +252,18 @@ void worker_loop(qg_server* sv) {
       any_busy = progressed = true;
     }
     std::unique_lock<std::mutex> lk(sv->mu);
-    if (sv->stop && sv->pending.empty() && !any_busy) break;
+    if (sv->stop && sv->npending == 0 && !any_busy) break;
     if (sv->error != QG_OK && !any_busy) {
       // a failed server completes nothing more: drop what waits
-      sv->pending.clear();
+      for (auto& d : sv->pending) d.clear();
+      sv->npending = 0;
       if (sv->stop) break;
     }
     if (!progressed) {
       if (any_busy) {
         lk.unlock();
         std::this_thread::yield();  // a batch is in flight: poll its event again soon
-      } else if (sv->pending.empty() && !sv->stop) {
+      } else if (sv->npending == 0 && !sv->stop) {
         sv->cv.wait_for(lk, std::chrono::milliseconds(50));
       }
     }
@@ -291,7 +321,8 @@ int qg_server_submit(qg_server* sv, const float* query, int32_t k, int32_t ef, u
     if (sv->error != QG_OK) return qgi::set_error(sv->error, sv->errmsg);
     if (sv->stop) return qgi::set_error(QG_EINVAL, "server is stopping");
     r.t_submit = now_s();
-    sv->pending.push_back(std::move(r));
+    sv->pending[ef_class(ef)].push_back(std::move(r));
+    ++sv->npending;
     ++sv->submitted;
   }
   sv->cv.notify_one();
@@ -302,18 +333,23 @@ int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32
                        double* latency_s) {
   if (!sv || max_results < 0) return qgi::set_error(QG_EINVAL, "server is NULL or max_results < 0");
   std::lock_guard<std::mutex> lk(sv->mu);
-  const int64_t n = std::min<int64_t>(max_results, (int64_t)sv->done.size());
   const size_t K = (size_t)sv->k_max;
-  for (int64_t i = 0; i < n; ++i) {
-    const Result& r = sv->done.front();
-    if (tags) tags[i] = r.tag;
-    if (latency_s) latency_s[i] = r.latency;
-    for (size_t j = 0; j < K; ++j) {
-      const bool in = j < (size_t)r.k;
-      if (ids) ids[i * K + j] = in ? r.ids[j] : -1;
-      if (dists) dists[i * K + j] = in ? r.dists[j] : __builtin_inff();
+  int64_t n = 0;
+  while (n < max_results && !sv->done.empty()) {
+    DoneBatch& b = sv->done.front();
+    while (n < max_results && b.next < b.tags.size()) {
+      const size_t r = b.next++;
+      if (tags) tags[n] = b.tags[r];
+      if (latency_s) latency_s[n] = b.latency[r];
+      const size_t k = (size_t)b.ks[r];
+      for (size_t j = 0; j < K; ++j) {
+        const bool in = j < k;
+        if (ids) ids[n * K + j] = in ? b.ids[r * K + j] : -1;
+        if (dists) dists[n * K + j] = in ? b.dists[r * K + j] : __builtin_inff();
+      }
+      ++n;
     }
-    sv->done.pop_front();
+    if (b.next == b.tags.size()) sv->done.pop_front();
   }
   return n;
 }
