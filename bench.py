@@ -28,6 +28,18 @@ METRIC = "QPS at recall@10=0.95 (1M×128 fp32), learned-stop vs fixed-ef, 1 GPU"
 EFS = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 
+def kernel_code_hash(path: str) -> str:
+    """sha256 prefix of a source file's code: comments and blank space removed,
+    so that a measurement stays attached to the code it measured."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"\s+", " ", text).strip()
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -66,23 +78,23 @@ def main():
     from paper_2411_12229_amd import qg
 
     dev = torch.device("cuda:0")
-    cfg = synth.CONFIGS[2]
+    cfg = synth.CONFIGS[synth.SIFT_LIKE]
     D, R, k = cfg.D, cfg.R, cfg.k
     if args.load_index:
         if not args.ef:
             sys.exit("--load-index needs --ef")
-        _, Q = synth.gen_data(2, n=1, nq=args.nq)  # queries do not depend on n
+        _, Q = synth.gen_data(synth.SIFT_LIKE, n=1, nq=args.nq)  # queries do not depend on n
         idx = qg.qg_load_index(args.load_index)
         X = G = M = entry = gt = None
         Qd = torch.from_numpy(Q).to(dev)
         log(f"[bench] loaded {args.load_index}: {idx.n} blocks")
     else:
         t0 = time.time()
-        X, Q = synth.gen_data(2, n=args.n, nq=args.nq)
-        M = synth.rotation(D, synth.seed(2, "rotation"))
+        X, Q = synth.gen_data(synth.SIFT_LIKE, n=args.n, nq=args.nq)
+        M = synth.rotation(D, synth.seed(synth.SIFT_LIKE, "rotation"))
         log(f"[bench] data {X.shape} queries {Q.shape} in {time.time() - t0:.1f}s")
         t0 = time.time()
-        G = synth.knn_graph(X, R, synth.seed(2, "long"), device=dev)
+        G = synth.knn_graph(X, R, synth.seed(synth.SIFT_LIKE, "long"), device=dev)
         entry = synth.medoid(X)
         log(f"[bench] input graph (k-NN + random links) in {time.time() - t0:.1f}s; entry {entry}")
         Xd, Gd, Md, Qd = (torch.from_numpy(a).to(dev) for a in (X, G, M, Q))
@@ -187,7 +199,7 @@ def main():
     if not args.no_learned_stop and gt is not None:
         from paper_2411_12229_amd import learned_stop
         t0 = time.time()
-        _, Qtr = synth.gen_data(2, n=1, nq=20_000, qseed=synth.seed(2, "train"))
+        _, Qtr = synth.gen_data(synth.SIFT_LIKE, n=1, nq=20_000, qseed=synth.seed(synth.SIFT_LIKE, "train"))
         gt_tr, _ = synth.ground_truth(X, Qtr, k, device=dev)
         Qtr_d, gt_tr_d = torch.from_numpy(Qtr).to(dev), torch.from_numpy(gt_tr).to(dev)
         t_min = 8
@@ -287,7 +299,7 @@ def main():
         with open(os.path.join(ROOT, "profiles", "search_kernel_traffic.json")) as f:
             tr = json.load(f)
         src = os.path.join(ROOT, "paper_2411_12229_amd", "csrc", "qg_kernels.hip")
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = kernel_code_hash(src)
         if tr.get("kernel_source_sha256_prefix") == sha and tr.get("ef") == ef and args.nq == 10_000 \
                 and args.n == 1_000_000:
             roofline["traffic"] = tr["traffic_bytes"]

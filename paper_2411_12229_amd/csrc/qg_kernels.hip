@@ -710,7 +710,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   };
   const float delta = build_lut<D, R>(a.qrot + q * D, lut);
 
-  // S starts with the entry keyed by its exact distance (reading S13).
+  // S starts with the entry, keyed by its exact distance (no estimate exists for it).
   float de;
   {
     BV e;
@@ -724,8 +724,9 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   float nn_wk = 0.0f;  // worst (distance, id) of NN once it holds k entries
   uint32_t nn_wi = 0;
   int expansions = 0, pops = 0, appended = 0;
-  // Next-vertex prefetch (Sec. 3.1.4): once the new candidates are ranked,
-  // the next pop is known, and its block is loaded while the beam is updated.
+  // Next-vertex prefetch (Sec. 3.1.4): the next vertex to expand is the smaller
+  // of the best new candidate and the next unchecked, unvisited old entry; its
+  // block is loaded while NN and the beam are updated.
   BV nxt;
   uint32_t nxt_id = kEmpty;
   int since = 0, nevals = 0;  // learned stop: expansions since NN changed, evaluations so far

@@ -33,6 +33,9 @@ class Config:
     note: str = ""
 
 
+# The synthetic workloads, by what they stand in for.
+TINY, SIFT_LIKE, GIST_LIKE, UNIT768, DEEP_LIKE = 1, 2, 3, 4, 5
+
 CONFIGS = {
     1: Config(1, 10_000, 128, 32, 200, 10, (64,), "16-cluster Gaussian mixture, sigma 0.3"),
     2: Config(2, 1_000_000, 128, 32, 10_000, 10, (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512),

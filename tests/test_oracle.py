@@ -203,7 +203,8 @@ def test_obar_o_range_and_mean():
 
 def test_degenerate_edge_is_exact():
     """A neighbour equal to its holder (r = 0) gets a zero code and factors so
-    that its estimate is exactly the holder's distance (reading S5)."""
+    that its estimate is exactly the holder's distance (the paper leaves the
+    0/0 of this degenerate edge open)."""
     rng = np.random.default_rng(2)
     X = rng.standard_normal((5, 64)).astype(np.float32)
     X[4] = X[1]
