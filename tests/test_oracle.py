@@ -219,7 +219,7 @@ def test_degenerate_edge_is_exact():
 
 def test_estimate_at_self_is_near_zero():
     """q_r = o_r: the float estimate is 0 up to rounding, the quantised one is
-    within the quantisation bound |f_rescale| * Delta * D / 2 (reading P3/P7)."""
+    within the quantisation bound |f_rescale| * Delta * D / 2."""
     X, M, G, e = _tiny_index()
     D, R = X.shape[1], G.shape[1]
     blocks = oracle.encode(X, G, M)
@@ -259,7 +259,7 @@ def test_zero_query_quantises_to_zero():
 
 def test_integer_vs_float_estimator_bound():
     """|Delta*S - sum (2b-1) q'_i| <= Delta*D/2, so the quantised estimate is
-    within |f_rescale| * Delta * D / 2 of the unquantised one (P7)."""
+    within |f_rescale| * Delta * D / 2 of the unquantised one."""
     X, M, G, e = _tiny_index()
     D, R = X.shape[1], G.shape[1]
     blocks = oracle.encode(X, G, M)
@@ -308,7 +308,7 @@ def test_estimator_unbiased_and_error_scale():
 def test_search_exhaustive_beam_is_brute_force():
     """With ef large enough that nothing is ever truncated, Algorithm 1 visits
     every vertex reachable from the entry, so implicit re-ranking returns the
-    exact k nearest neighbours (P9)."""
+    exact k nearest neighbours."""
     X, M, G, e = _tiny_index(N=400, D=64, R=16)
     assert synth.reachable(G, e) == 400
     blocks = oracle.encode(X, G, M)
@@ -349,7 +349,7 @@ def _textbook_beam_search(X, G, e, q, ef, k):
 
 def test_search_control_flow_equals_textbook_beam_search():
     """Replacing the estimator by the exact distance and letting a vertex enter
-    the beam once turns Algorithm 1 into the vanilla search of Sec. 2.1 (P10)."""
+    the beam once turns Algorithm 1 into the vanilla search of Sec. 2.1."""
     X, M, G, e = _tiny_index(N=500, D=64, R=16)
     blocks = oracle.encode(X, G, M)
     Q = np.random.default_rng(10).standard_normal((6, 64)).astype(np.float32)
@@ -376,7 +376,7 @@ def test_search_padding_and_small_ef():
 
 
 def test_search_deterministic_and_batch_independent():
-    """P13: two runs are identical and a query alone equals the same query in a batch."""
+    """Two runs are identical and a query alone equals the same query in a batch."""
     X, M, G, e = _tiny_index(N=400, D=64, R=16)
     blocks = oracle.encode(X, G, M)
     Q = np.random.default_rng(11).standard_normal((12, 64)).astype(np.float32)
@@ -389,7 +389,7 @@ def test_search_deterministic_and_batch_independent():
 
 
 def test_recall_trends_config1():
-    """Soft trends (P14): recall rises with the beam size (Sec. 2.1) and
+    """Soft trends: recall rises with the beam size (Sec. 2.1) and
     multiple estimates beat a single estimate per vertex (Sec. 4.2.3)."""
     X, Q = synth.gen_data(1, n=3000, nq=60)
     M = synth.rotation(128, synth.seed(1, "rotation"))
@@ -408,7 +408,7 @@ def test_recall_trends_config1():
 def test_build_graph_invariants():
     """Algorithm 2 with refinement: every vertex has exactly R distinct
     non-self out-neighbours (Sec. 3.2.2, Table 5 caption) and every vertex is
-    reachable from the entry (P12)."""
+    reachable from the entry."""
     X, _ = synth.gen_data(1, n=1500, nq=1)
     N, D, R = 1500, 128, 32
     M = synth.rotation(D, 3)
