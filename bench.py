@@ -127,7 +127,8 @@ def main():
 
     sweep = []
     chosen = None
-    for ef in ((args.ef,) if args.ef else EFS):
+
+    def measure(ef):
         ids, dists, st = run(ef, stats=True)
         rec = synth.recall(ids.cpu().numpy(), gt, k) if gt is not None else float("nan")
         s = st.cpu().numpy()
@@ -140,10 +141,23 @@ def main():
                       "overflow_queries": int(s[:, 3].sum())})
         log(f"[bench] ef={ef:4d} recall@10={rec:.4f} E_q mean {s[:, 0].mean():.1f} max {s[:, 0].max()} "
             f"~{qps:,.0f} q/s")
+        return rec, s
+
+    for ef in ((args.ef,) if args.ef else EFS):
+        rec, s = measure(ef)
         if chosen is None and (rec >= args.target or args.ef):
             chosen = (ef, rec, s)
             if len(sweep) >= 2 and ef >= 64:
                 break
+    # the coarse grid brackets the target recall between two beam sizes; the
+    # smallest one that reaches it is found between them in steps of 8
+    if chosen is not None and not args.ef and len(sweep) >= 2 and sweep[-2]["recall@10"] < args.target:
+        for ef in range(sweep[-2]["ef"] + 8, chosen[0], 8):
+            rec, s = measure(ef)
+            if rec >= args.target:
+                chosen = (ef, rec, s)
+                break
+        sweep.sort(key=lambda r: r["ef"])
     if chosen is None:
         ef, rec, s = EFS[-1], sweep[-1]["recall@10"], None
         log(f"[bench] recall target {args.target} not reached; timing ef={ef}")

@@ -75,37 +75,53 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// x from lane (lane ^ s) for s = 1, 2 (DPP quad permutes) and 4, 8, 16 (LDS
-// swizzle in bit mode, xor within 32 lanes).  Pure data movement.
+// x from lane (lane ^ s) for s = 1, 2 (DPP quad permutes).  Pure data movement.
 template <int S>
 __device__ __forceinline__ int xor_lane_i(int v) {
-  static_assert(S == 1 || S == 2 || S == 4 || S == 8 || S == 16, "xor distance");
+  static_assert(S == 1 || S == 2, "xor distance");
   if constexpr (S == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
-  if constexpr (S == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
-  return __builtin_amdgcn_ds_swizzle(v, (S << 10) | 0x1F);
+  return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
 }
 template <int S>
 __device__ __forceinline__ float xor_lane(float x) { return __int_as_float(xor_lane_i<S>(__float_as_int(x))); }
 
-// The pair {x[l], x[l ^ 32]} in every lane l, through the gfx950 lane swap of
-// the two wavefront halves (which of the two comes first depends on the half;
+// x from lane (lane + s) mod 16 within its row of 16 lanes (DPP row rotation),
+// s = 4 or 8.  For s = 8 that lane is lane ^ 8.
+template <int S>
+__device__ __forceinline__ float row_ror(float x) {
+  static_assert(S == 4 || S == 8, "rotation");
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x120 | S, 0xF, 0xF, false));
+}
+
+// The pair {x[l], x[l ^ 32]} (pair32) or {x[l], x[l ^ 16]} (pair16) in every
+// lane l, through the gfx950 swaps of the two wavefront halves and of the odd
+// and even rows of 16 lanes (which of the two comes first depends on the lane;
 // only symmetric combinations of the pair are used).
 __device__ __forceinline__ void pair32(float x, float& a, float& b) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
   a = __uint_as_float(r[0]);
   b = __uint_as_float(r[1]);
 }
+__device__ __forceinline__ void pair16(float x, float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
 
 // Butterfly sum p[l] + p[l ^ s] for s = 32, 16, ..., 1; every lane ends with
 // the total.  Floating-point addition is commutative, so each stage adds
-// exactly the pair the stage names whatever the order within the pair.
+// exactly the pair the stage names whatever the order within the pair.  The
+// stage of 4 takes its partner from the rotation by 4: after the stage of 8,
+// lanes l and l ^ 8 hold the same bits, and the rotated-in lane (l + 4) mod 16
+// is l ^ 4 or l ^ 12.  No stage goes through LDS.
 __device__ __forceinline__ float butterfly_f(float p) {
   float a, b;
   pair32(p, a, b);
   p = a + b;
-  p = p + xor_lane<16>(p);
-  p = p + xor_lane<8>(p);
-  p = p + xor_lane<4>(p);
+  pair16(p, a, b);
+  p = a + b;
+  p = p + row_ror<8>(p);
+  p = p + row_ror<4>(p);
   p = p + xor_lane<2>(p);
   p = p + xor_lane<1>(p);
   return p;
@@ -115,9 +131,10 @@ __device__ __forceinline__ float wave_max(float v) {
   float a, b;
   pair32(v, a, b);
   v = fmaxf(a, b);
-  v = fmaxf(v, xor_lane<16>(v));
-  v = fmaxf(v, xor_lane<8>(v));
-  v = fmaxf(v, xor_lane<4>(v));
+  pair16(v, a, b);
+  v = fmaxf(a, b);
+  v = fmaxf(v, row_ror<8>(v));
+  v = fmaxf(v, row_ror<4>(v));
   v = fmaxf(v, xor_lane<2>(v));
   v = fmaxf(v, xor_lane<1>(v));
   return v;
@@ -431,8 +448,11 @@ struct Visited {
   }
 };
 
+// Membership test.  For the LDS hash, end receives the slot where the probe
+// stopped: when id is absent, the first empty slot of its probe sequence,
+// which is where inserting id puts it.
 template <bool GV>
-__device__ __forceinline__ bool visited_contains(const Visited& v, uint32_t id) {
+__device__ __forceinline__ bool visited_probe(const Visited& v, uint32_t id, uint32_t& end) {
   if constexpr (GV) {
     uint32_t w = __hip_atomic_load(v.bits + (id >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return (w >> (id & 31)) & 1u;
@@ -443,8 +463,14 @@ __device__ __forceinline__ bool visited_contains(const Visited& v, uint32_t id) 
       s = (s + 1) & v.mask;
       e = v.tab[s];
     }
+    end = s;
     return e == id;
   }
+}
+template <bool GV>
+__device__ __forceinline__ bool visited_contains(const Visited& v, uint32_t id) {
+  uint32_t end;
+  return visited_probe<GV>(v, id, end);
 }
 
 // Insert id (wave-uniform); returns true if it was already present.
@@ -739,7 +765,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     // (o2u, for the stop features) and the next one still to be expanded (o2f,
     // the prefetch target).
     int c = -1;
-    uint32_t p = 0;
+    uint32_t p = 0, p_slot = 0;  // p_slot: p's free hash slot, found by the probe below
     uint64_t o2u = kNone, o2f = kNone;
     bool o2u_known = false, o2f_known = false;
     while (cursor < size) {
@@ -752,7 +778,8 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         continue;
       }
       bool fresh = false;
-      if (un) fresh = !visited_contains<GV>(vis, (uint32_t)e);
+      uint32_t vend = 0;
+      if (un) fresh = !visited_probe<GV>(vis, (uint32_t)e, vend);
       const uint64_t mf = ballot(fresh);
       const uint64_t dups = mf ? mu & ((1ull << first_lane(mf)) - 1) : mu;
       if (dups) {
@@ -766,6 +793,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       const int f = first_lane(mf);
       c = cursor + f;
       p = rdlane((uint32_t)e, f);
+      if constexpr (!GV) p_slot = rdlane(vend, f);
       const uint64_t later = f == 63 ? 0ull : ~0ull << (f + 1);
       const uint64_t mu2 = mu & later, mf2 = mf & later & ballot((uint32_t)e != p);
       if (mu2) {
@@ -783,7 +811,12 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     beam_lo[2 * c] = p | kChecked;  // every lane stores the same word
     cursor = c + 1;
     ++pops;
-    visited_insert<GV>(vis, p, lane);  // p is not in the set: a new slot
+    if constexpr (GV) {
+      visited_insert<GV>(vis, p, lane);
+    } else {
+      if (lane == 0) vis.tab[p_slot] = p;  // p is absent: its probe ended at this empty slot
+      wave_sync();
+    }
     if (++nvis > vis_limit) {  // on-chip visited set full: hand the query to the overflow path
       if (lane == 0) {
         const int slot = atomicAdd(a.counters + 1, 1);
