@@ -756,6 +756,11 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   BV nxt;
   uint32_t nxt_id = kEmpty;
   int since = 0, nevals = 0;  // learned stop: expansions since NN changed, evaluations so far
+  // NN (ascending (distance, id)): for k <= 64 lane i holds entry i in
+  // registers; larger k keep it in LDS (nkey, nid).
+  const bool nn_in_regs = k <= 64;
+  float nrk = 0.0f;
+  uint32_t nri = 0;
 
   for (;;) {
     // pop the first unchecked entry whose vertex is not visited yet.  Unchecked
@@ -896,38 +901,59 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     ++since;
     if (nnc < k || kv_less(dp, p, nn_wk, nn_wi)) {
       since = 0;
-      int pos = 0;
-      for (int base = 0; base < nnc; base += 64) {
-        const int i = base + lane;
-        const bool lt = (i < nnc) && kv_less(nkey[i < nnc ? i : 0], nid[i < nnc ? i : 0], dp, p);
-        pos += __popcll(ballot(lt));
-      }
-      const int last = nnc < k ? nnc : k - 1;  // entries [pos, last) move up by one
-      for (int base = ((last - 1) >> 6) << 6; base >= 0 && last > pos; base -= 64) {
-        const int i = base + lane;
-        float kk = 0.0f;
-        uint32_t ii = 0;
-        const bool mv = (i >= pos) && (i < last);
-        if (mv) {
-          kk = nkey[i];
-          ii = nid[i];
+      if (nn_in_regs) {
+        // entries [pos, last) move up one lane (DPP shift of the wavefront by one lane)
+        const int pos = (int)__popcll(ballot(lane < nnc && kv_less(nrk, nri, dp, p)));
+        const int last = nnc < k ? nnc : k - 1;
+        const float upk = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(nrk), 0x138, 0xF, 0xF, false));
+        const uint32_t upi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nri, 0x138, 0xF, 0xF, false);
+        if (lane > pos && lane <= last) {
+          nrk = upk;
+          nri = upi;
         }
-        wave_sync();
-        if (mv) {
-          nkey[i + 1] = kk;
-          nid[i + 1] = ii;
+        if (lane == pos) {
+          nrk = dp;
+          nri = p;
         }
+        nnc = nnc < k ? nnc + 1 : k;
+        if (nnc == k) {
+          nn_wk = rdlane(nrk, k - 1);
+          nn_wi = rdlane(nri, k - 1);
+        }
+      } else {
+        int pos = 0;
+        for (int base = 0; base < nnc; base += 64) {
+          const int i = base + lane;
+          const bool lt = (i < nnc) && kv_less(nkey[i < nnc ? i : 0], nid[i < nnc ? i : 0], dp, p);
+          pos += __popcll(ballot(lt));
+        }
+        const int last = nnc < k ? nnc : k - 1;  // entries [pos, last) move up by one
+        for (int base = ((last - 1) >> 6) << 6; base >= 0 && last > pos; base -= 64) {
+          const int i = base + lane;
+          float kk = 0.0f;
+          uint32_t ii = 0;
+          const bool mv = (i >= pos) && (i < last);
+          if (mv) {
+            kk = nkey[i];
+            ii = nid[i];
+          }
+          wave_sync();
+          if (mv) {
+            nkey[i + 1] = kk;
+            nid[i + 1] = ii;
+          }
+          wave_sync();
+          if (base < pos) break;
+        }
+        pos = uni(pos);
+        nkey[pos] = dp;  // same value from every lane
+        nid[pos] = p;
         wave_sync();
-        if (base < pos) break;
-      }
-      pos = uni(pos);
-      nkey[pos] = dp;  // same value from every lane
-      nid[pos] = p;
-      wave_sync();
-      nnc = nnc < k ? nnc + 1 : k;
-      if (nnc == k) {
-        nn_wk = uni(nkey[k - 1]);
-        nn_wi = uni(nid[k - 1]);
+        nnc = nnc < k ? nnc + 1 : k;
+        if (nnc == k) {
+          nn_wk = uni(nkey[k - 1]);
+          nn_wi = uni(nid[k - 1]);
+        }
       }
     }
 
@@ -1027,7 +1053,8 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     if constexpr (has_stop<LS>) {
       if (expansions >= a.ls_t_min && (expansions - a.ls_t_min) % a.ls_t_every == 0) {
         StopFeatures F;
-        const float nn1 = uni(nkey[0]), nnk = uni(nkey[nnc - 1]);
+        const float nn1 = nn_in_regs ? rdlane(nrk, 0) : uni(nkey[0]);
+        const float nnk = nn_in_regs ? rdlane(nrk, nnc - 1) : uni(nkey[nnc - 1]);
         F.compute(expansions, pops, nnc, k, since, de, nn1, nnk, bfk, size, ef, dp, app, R);
         float out;
         if constexpr (LS == kLsStop)
@@ -1038,7 +1065,11 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
           if (nevals < a.tr_max) {
             const int64_t slot = q * a.tr_max + nevals;
             if (lane < 16) a.tr_feat[slot * 16 + lane] = F.mine;
-            for (int i = lane; i < k; i += 64) a.tr_nn[slot * k + i] = i < nnc ? (int32_t)nid[i] : -1;
+            for (int i = lane; i < k; i += 64) {
+              int32_t id = -1;
+              if (i < nnc) id = nn_in_regs ? (int32_t)nri : (int32_t)nid[i];
+              a.tr_nn[slot * k + i] = id;
+            }
             if (lane == 0) a.tr_out[slot] = out;
           }
           ++nevals;
@@ -1054,8 +1085,14 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   // answer: NN ascending by (distance, id), padded with (-1, inf)
   const int k_out = LS == kMixed ? a.k_out : k;  // a mixed batch's rows are k_out wide
   for (int i = lane; i < k_out; i += 64) {
-    a.out_ids[q * k_out + i] = i < nnc ? (int32_t)nid[i] : -1;
-    a.out_dists[q * k_out + i] = i < nnc ? nkey[i] : __builtin_inff();
+    int32_t id = -1;
+    float d = __builtin_inff();
+    if (i < nnc) {
+      id = nn_in_regs ? (int32_t)nri : (int32_t)nid[i];
+      d = nn_in_regs ? nrk : nkey[i];
+    }
+    a.out_ids[q * k_out + i] = id;
+    a.out_dists[q * k_out + i] = d;
   }
   if (a.out_stats && lane == 0) {
     int32_t* st = a.out_stats + 4 * q;
