@@ -160,12 +160,22 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
  * workgroup (1, 2, 4, 8; halved at launch while the LDS does not fit) and
  * visited-hash size (2^h >= F * ef slots, F = 2, 3, 4; a smaller table leaves
  * room for more wavefronts, a larger one sends fewer queries to the overflow
- * pass) and keeps the fastest for later searches of this index.  Results do
- * not depend on the choice, only the speed.  Outputs (host, nullable): the
- * chosen wavefronts per workgroup and F, and the best time in ms of one
- * qg_search_ex call.  Synchronous; allocates and frees temporary outputs. */
+ * pass), then, for the fastest pair, caps of 24, 20 and 16 resident
+ * wavefronts per compute unit against no cap (a batch only a little larger
+ * than the resident query slots can finish sooner on fewer, less contended
+ * slots).  The fastest setting is kept for later searches of this index.
+ * Results do not depend on the choice, only the speed.  Outputs (host,
+ * nullable): the chosen wavefronts per workgroup, F, the cap (0 = none) and
+ * the best time in ms of one qg_search_ex call.  Synchronous; allocates and
+ * frees temporary outputs. */
 int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
-                int32_t *out_wpb, int32_t *out_hash_factor, double *out_ms);
+                int32_t *out_wpb, int32_t *out_hash_factor, int32_t *out_cu_waves, double *out_ms);
+
+/* Set the launch shape directly (as qg_autotune would): wavefronts per
+ * workgroup (1, 2, 4 or 8), visited-hash factor F (2, 3 or 4) and the cap on
+ * resident wavefronts per compute unit (0 = none, at most 64).  Results do
+ * not depend on it.  QG_EINVAL for values outside these sets. */
+int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves);
 
 /* ---- Serving loop (continuous batching) ----------------------------------
  * A server owns `streams` slots over one index.  Each slot has its own

@@ -82,6 +82,7 @@ struct qg_index {
   // halved while the LDS does not fit) and visited-hash slots per beam entry
   int wpb_pref = 4;
   int hash_factor = 3;
+  int cu_waves = 0;  // cap on resident wavefronts per compute unit (0 = as many as fit)
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev[2];  // pairs per kernel class
@@ -189,6 +190,7 @@ qg_index* make_view(const qg_index* base) {
   v->blocks = base->blocks;
   v->wpb_pref = base->wpb_pref;
   v->hash_factor = base->hash_factor;
+  v->cu_waves = base->cu_waves;
   v->fb_slots = base->fb_slots;
   v->fb_words = base->fb_words;
   if (hipMalloc(&v->counters, sizeof(int) * kCounters) != hipSuccess ||
@@ -504,6 +506,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   const size_t lds = (size_t)wpb * L.total + extra;
   int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, wpb, lds);
   if (occ <= 0) occ = 1;
+  if (idx->cu_waves > 0) occ = std::min(occ, std::max(1, idx->cu_waves / wpb));
   int64_t want = (nq + wpb - 1) / wpb;
   int grid = (int)std::min<int64_t>(want, (int64_t)occ * 256);
 
@@ -534,15 +537,15 @@ int qg_search_mixed(const qg_index* idx, const float* queries, int64_t nq, const
 }
 
 int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
-                int32_t* out_wpb, int32_t* out_hash_factor, double* out_ms) {
+                int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, double* out_ms) {
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (nq <= 0 || !queries) return fail(QG_EINVAL, "autotuning needs queries");
   DeviceGuard g(idx->device);
   int32_t* ids = nullptr;
   float* dists = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const int keep_wpb = idx->wpb_pref, keep_hf = idx->hash_factor;
-  int best_wpb = keep_wpb, best_hf = keep_hf, rc = QG_OK;
+  const int keep_wpb = idx->wpb_pref, keep_hf = idx->hash_factor, keep_cw = idx->cu_waves;
+  int best_wpb = keep_wpb, best_hf = keep_hf, best_cw = 0, rc = QG_OK;
   double best = -1.0;
   auto cleanup = [&]() {
     if (e0) (void)hipEventDestroy(e0);
@@ -556,22 +559,30 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
     cleanup();
     return fail(QG_ENOMEM, "autotune buffers");
   }
+  // one untimed call, then the best of three timed ones
+  auto time_it = [&](double& t) {
+    t = -1.0;
+    if ((rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr))) return;
+    for (int rep = 0; rep < 3 && rc == QG_OK; ++rep) {
+      float ms = 0.0f;
+      if (hipEventRecord(e0, idx->stream) != hipSuccess) rc = fail(QG_EDEVICE, "hipEventRecord");
+      if (!rc) rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr);
+      if (!rc && (hipEventRecord(e1, idx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(QG_EDEVICE, "timing events");
+      if (!rc && (t < 0 || ms < t)) t = ms;
+    }
+  };
+  // workgroup shape and hash size at full residency, then a cap on resident
+  // wavefronts per compute unit for that shape (a batch only slightly larger
+  // than the resident slots can finish sooner with fewer, less contended slots)
+  idx->cu_waves = 0;
   for (int wpb : {1, 2, 4, 8}) {
     for (int hf : {2, 3, 4}) {
       idx->wpb_pref = wpb;
       idx->hash_factor = hf;
-      // one untimed call, then the best of three timed ones
-      if ((rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr))) break;
-      double t = -1.0;
-      for (int rep = 0; rep < 3 && rc == QG_OK; ++rep) {
-        float ms = 0.0f;
-        if (hipEventRecord(e0, idx->stream) != hipSuccess) rc = fail(QG_EDEVICE, "hipEventRecord");
-        if (!rc) rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr);
-        if (!rc && (hipEventRecord(e1, idx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          rc = fail(QG_EDEVICE, "timing events");
-        if (!rc && (t < 0 || ms < t)) t = ms;
-      }
+      double t;
+      time_it(t);
       if (rc) break;
       if (best < 0 || t < best) {
         best = t;
@@ -581,13 +592,40 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
     }
     if (rc) break;
   }
+  if (!rc) {
+    idx->wpb_pref = best_wpb;
+    idx->hash_factor = best_hf;
+    for (int cw : {24, 20, 16}) {
+      idx->cu_waves = cw;
+      double t;
+      time_it(t);
+      if (rc) break;
+      if (t < best) {
+        best = t;
+        best_cw = cw;
+      }
+    }
+  }
   cleanup();
   idx->wpb_pref = rc ? keep_wpb : best_wpb;
   idx->hash_factor = rc ? keep_hf : best_hf;
+  idx->cu_waves = rc ? keep_cw : best_cw;
   if (rc) return rc;
   if (out_wpb) *out_wpb = best_wpb;
   if (out_hash_factor) *out_hash_factor = best_hf;
+  if (out_cu_waves) *out_cu_waves = best_cw;
   if (out_ms) *out_ms = best;
+  return QG_OK;
+}
+
+int qg_set_launch(qg_index* idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(QG_EINVAL, "wavefronts per workgroup not 1, 2, 4 or 8");
+  if (hash_factor < 2 || hash_factor > 4) return fail(QG_EINVAL, "hash factor not 2, 3 or 4");
+  if (cu_waves < 0 || cu_waves > 64) return fail(QG_EINVAL, "resident wavefront cap out of range");
+  idx->wpb_pref = wpb;
+  idx->hash_factor = hash_factor;
+  idx->cu_waves = cu_waves;
   return QG_OK;
 }
 

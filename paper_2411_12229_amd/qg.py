@@ -60,7 +60,8 @@ def _load():
         "qg_copy_blocks": ([P, i64, i64, P], c_int),
         "qg_set_stream": ([P, P], c_int),
         "qg_reserve": ([P, i64], c_int),
-        "qg_autotune": ([P, P, i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+        "qg_set_launch": ([P, i32, i32, i32], c_int),
+        "qg_autotune": ([P, P, i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                          ctypes.POINTER(ctypes.c_double)], c_int),
         "qg_index_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)], c_int),
@@ -132,12 +133,17 @@ class Index:
         _check(_lib.qg_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)))
 
     def autotune(self, queries: torch.Tensor, k: int, ef: int, flags: int = 0):
-        """Pick the launch shape (wavefronts per workgroup, visited-hash factor) by timing searches of
-        these queries; returns (wpb, hash_factor, best ms per call)."""
-        w, h, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        """Pick the launch shape (wavefronts per workgroup, visited-hash factor, cap on resident
+        wavefronts per compute unit) by timing searches of these queries; returns
+        (wpb, hash_factor, cu_waves (0 = no cap), best ms per call)."""
+        w, h, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(_lib.qg_autotune(self._h, _dev(queries, torch.float32, "queries"), queries.shape[0], k, ef, flags,
-                                ctypes.byref(w), ctypes.byref(h), ctypes.byref(ms)))
-        return w.value, h.value, ms.value
+                                ctypes.byref(w), ctypes.byref(h), ctypes.byref(c), ctypes.byref(ms)))
+        return w.value, h.value, c.value, ms.value
+
+    def set_launch(self, wpb: int, hash_factor: int, cu_waves: int = 0) -> None:
+        """Set the launch shape directly (the values qg_autotune picks)."""
+        _check(_lib.qg_set_launch(self._h, int(wpb), int(hash_factor), int(cu_waves)))
 
     def reserve(self, nq: int) -> None:
         """Size the query scratch for batches of up to nq queries (before capturing graphs)."""
