@@ -163,9 +163,10 @@ __device__ __forceinline__ float exact_dist(const float (&qv)[DPL], const float 
 __global__ __launch_bounds__(64) void rotate_kernel(const float* __restrict__ in, int64_t n, int D,
                                                     const float* __restrict__ M, float* __restrict__ out,
                                                     int* __restrict__ zero, int nzero) {
-  // the tile's 16 input rows and 16 rows of M, 128 columns at a time, staged
-  // through LDS with coalesced loads (rows padded to 132 floats)
-  constexpr int KC = 128, LD = KC + 4;
+  // the tile's 16 input rows and 16 rows of M, 64 columns at a time, staged
+  // through LDS with coalesced loads (rows padded to 68 floats); the next
+  // chunk's loads are issued before this chunk's products
+  constexpr int KC = 64, LD = KC + 4;
   __shared__ float As[16 * LD], Bs[16 * LD];
   const int lane = threadIdx.x;
   if (zero && blockIdx.x == 0 && blockIdx.y == 0 && lane < nzero) zero[lane] = 0;
@@ -173,29 +174,27 @@ __global__ __launch_bounds__(64) void rotate_kernel(const float* __restrict__ in
   const int i0 = blockIdx.y * 16;
   const int rl = lane & 15, kk = lane >> 4;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < D; k0 += KC) {
+  float va[16], vb[16];
+  auto load = [&](int k0) {
     const int kw = D - k0 < KC ? D - k0 : KC;  // a multiple of 16
-    // every load of the chunk is issued before the first store; columns past
-    // kw re-read column kw - 1 and land in the unread part of the row
-    float va[16][2], vb[16][2];
+    const int c = min(lane, kw - 1);  // columns past kw re-read column kw - 1 into the unread part of the row
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t ra = r0 + r < n ? r0 + r : 0;  // rows past n only feed outputs that are not stored
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = min(lane + 64 * h, kw - 1);
-        va[r][h] = in[ra * D + k0 + c];
-        vb[r][h] = M[(int64_t)(i0 + r) * D + k0 + c];
-      }
+      va[r] = in[ra * D + k0 + c];
+      vb[r] = M[(int64_t)(i0 + r) * D + k0 + c];
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < D; k0 += KC) {
+    const int kw = D - k0 < KC ? D - k0 : KC;
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        As[r * LD + lane + 64 * h] = va[r][h];
-        Bs[r * LD + lane + 64 * h] = vb[r][h];
-      }
+    for (int r = 0; r < 16; ++r) {
+      As[r * LD + lane] = va[r];
+      Bs[r * LD + lane] = vb[r];
+    }
     __syncthreads();
+    if (k0 + KC < D) load(k0 + KC);
     for (int kb = 0; kb < kw; kb += 4)
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)As[rl * LD + kb + kk], (double)Bs[rl * LD + kb + kk], acc,
                                                  0, 0, 0);
