@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--ls-ef", type=int, default=0, help="beam size for the learned stop (default: the fixed ef)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shape instead of the one qg_autotune picks for the benchmark queries")
+    ap.add_argument("--launch", default="",
+                    help="wpb,hash_factor,cu_waves: set this launch shape for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -118,6 +120,11 @@ def main():
     with torch.cuda.stream(stream):
         Qs = Qd.clone()
     stream.synchronize()
+
+    shape = (4, 3, 0)  # the library's default launch shape
+    if args.launch:
+        shape = tuple(int(x) for x in args.launch.split(","))
+        idx.set_launch(*shape)
 
     def run(ef, stats=False):
         with torch.cuda.stream(stream):
@@ -191,9 +198,9 @@ def main():
         with torch.cuda.stream(stream):
             idx.search(Qs, k, ef)
 
-    tuned = None
-    shape = (4, 3, 0)  # the library's default launch shape
-    if not args.no_autotune:
+    tuned = {"waves_per_workgroup": shape[0], "hash_factor": shape[1], "resident_waves_per_cu_cap": shape[2],
+             "set_by": "--launch"} if args.launch else None
+    if not args.no_autotune and not args.launch:
         with torch.cuda.stream(stream):
             wpb_t, hf_t, cw_t, tms = idx.autotune(Qs, k, ef)
         shape = (wpb_t, hf_t, cw_t)
