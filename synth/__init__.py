@@ -100,25 +100,39 @@ def gen_data(cfg: int, n: int | None = None, nq: int | None = None, D: int | Non
             return out
 
         return draw(g, n), draw(gq, nq)
+    # configs 3-5 are drawn in float32, 32,768 rows at a time (the full sizes
+    # are 1M x 960, 1M x 768 and 5M x 96)
+    def chunked(m, row):
+        out = np.empty((m, D), np.float32)
+        for s in range(0, m, 1 << 15):
+            e = min(m, s + (1 << 15))
+            out[s:e] = row(e - s)
+        return out
+
+    f32 = np.float32
     if cfg == 3:
-        W = np.abs(g.standard_normal((D, 64))) / 8.0
+        W = (np.abs(g.standard_normal((D, 64))) / 8.0).astype(f32)
 
         def draw(gg, m):
-            z = np.abs(gg.standard_normal((m, 64)))
-            return np.maximum(0.0, z @ W.T + 0.05 * gg.standard_normal((m, D))).astype(np.float32)
+            return chunked(m, lambda b: np.maximum(f32(0.0), np.abs(gg.standard_normal((b, 64), dtype=f32)) @ W.T
+                                                   + f32(0.05) * gg.standard_normal((b, D), dtype=f32)))
 
         return draw(g, n), draw(gq, nq)
     if cfg == 4:
-        U = g.standard_normal((D, 128)) / math.sqrt(D)
-        X = _normalize(g.standard_normal((n, 128)) @ U.T + 0.06 * g.standard_normal((n, D)))
+        U = (g.standard_normal((D, 128)) / math.sqrt(D)).astype(f32)
+        X = chunked(n, lambda b: _normalize(g.standard_normal((b, 128), dtype=f32) @ U.T
+                                            + f32(0.06) * g.standard_normal((b, D), dtype=f32)))
         gvec = gq.standard_normal(128)
-        shift = 0.5 * math.sqrt(128) * gvec / np.linalg.norm(gvec)
-        Q = _normalize((gq.standard_normal((nq, 128)) + shift) @ U.T + 0.06 * gq.standard_normal((nq, D)))
+        shift = (0.5 * math.sqrt(128) * gvec / np.linalg.norm(gvec)).astype(f32)
+        Q = chunked(nq, lambda b: _normalize((gq.standard_normal((b, 128), dtype=f32) + shift) @ U.T
+                                             + f32(0.06) * gq.standard_normal((b, D), dtype=f32)))
         return X, Q
     if cfg == 5:
         mu = _normalize(g.standard_normal((4096, D)))
-        X = _normalize(mu[g.integers(0, 4096, n)] + 0.08 * g.standard_normal((n, D)))
-        Q = _normalize(mu[gq.integers(0, 4096, nq)] + 0.08 * gq.standard_normal((nq, D)))
+        X = chunked(n, lambda b: _normalize(mu[g.integers(0, 4096, b)]
+                                            + f32(0.08) * g.standard_normal((b, D), dtype=f32)))
+        Q = chunked(nq, lambda b: _normalize(mu[gq.integers(0, 4096, b)]
+                                             + f32(0.08) * gq.standard_normal((b, D), dtype=f32)))
         return X, Q
     raise ValueError(cfg)
 
