@@ -66,6 +66,11 @@ def main():
     ap.add_argument("--launch", default="",
                     help="wpb,hash_factor,cu_waves: set this launch shape for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--ls-study", action="store_true",
+                    help="instead of the benchmark line: learned stop against fixed ef at recall@10 0.90 / 0.95 / "
+                         "0.99 (one JSON line)")
+    ap.add_argument("--ls-workload", default="sift", choices=("sift", "unit768"),
+                    help="workload of --ls-study: the SIFT-shaped benchmark set or 1M x 768 unit-norm")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -80,6 +85,8 @@ def main():
     from paper_2411_12229_amd import qg
 
     dev = torch.device("cuda:0")
+    if args.ls_study:
+        return ls_study(args, dev)
     cfg = synth.CONFIGS[synth.SIFT_LIKE]
     D, R, k = cfg.D, cfg.R, cfg.k
     if args.load_index:
@@ -490,6 +497,112 @@ def main():
         "sweep": sweep,
     }
     print(json.dumps(out), flush=True)
+
+
+def ls_study(args, dev):
+    """Learned stop against fixed ef: for each recall@10 target, the smallest fixed beam that reaches it, and the
+    fastest learned-stop setting whose recall on the test queries reaches it.  Workloads: the SIFT-shaped
+    benchmark set, or 1M x 768 unit-norm (rank-128 data plus noise, queries from a mean-shifted copy).
+    Search-call throughput by host clock over `--steps` calls (rotation, search and overflow pass), inputs
+    resident on the device."""
+    import torch
+
+    import synth
+    from paper_2411_12229_amd import learned_stop, qg
+
+    c = synth.SIFT_LIKE if args.ls_workload == "sift" else synth.UNIT768
+    cfg = synth.CONFIGS[c]
+    D, R, k = cfg.D, cfg.R, cfg.k
+    t0 = time.time()
+    X, Q = synth.gen_data(c)
+    M = synth.rotation(D, synth.seed(c, "rotation"))
+    G = synth.knn_graph(X, R, synth.seed(c, "long"), device=dev)
+    entry = synth.medoid(X)
+    idx = qg.qg_build_index(torch.from_numpy(X).to(dev), torch.from_numpy(G).to(dev), torch.from_numpy(M).to(dev),
+                            entry)
+    gt, _ = synth.ground_truth(X, Q, k, device=dev)
+    _, Qtr = synth.gen_data(c, n=1, nq=20_000, qseed=synth.seed(c, "train"))
+    gt_tr, _ = synth.ground_truth(X, Qtr, k, device=dev)
+    del G
+    log(f"[ls-study] index {idx.n} x {D}, R={R}, ground truth in {time.time() - t0:.1f}s")
+    stream = torch.cuda.Stream()
+    idx.set_stream(stream)
+    with torch.cuda.stream(stream):
+        Qs = torch.from_numpy(Q).to(dev)
+        Qtr_d, gt_tr_d = torch.from_numpy(Qtr).to(dev), torch.from_numpy(gt_tr).to(dev)
+    stream.synchronize()
+    Qtrain, gtrain = Qtr_d[:16_000].contiguous(), gt_tr_d[:16_000]
+    Qth, gth = Qtr_d[16_000:].contiguous(), gt_tr_d[16_000:]
+
+    def rate(fn):
+        for _ in range(2):
+            fn()
+        stream.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        stream.synchronize()
+        return len(Q) * args.steps / (time.perf_counter() - t1)
+
+    cache = {}
+
+    def fixed(ef):
+        if ef not in cache:
+            with torch.cuda.stream(stream):
+                ids, _, st = idx.search(Qs, k, ef, stats=True)
+                rec = synth.recall(ids.cpu().numpy(), gt, k)
+                q = rate(lambda: idx.search(Qs, k, ef))
+            cache[ef] = {"ef": ef, "recall@10": round(rec, 4), "qps": round(q, 1),
+                         "mean_expansions": round(st[:, 0].float().mean().item(), 2)}
+            log(f"[ls-study] fixed ef={ef}: {cache[ef]}")
+        return cache[ef]
+
+    t_min, rows = 8, []
+    for target in (0.90, 0.95, 0.99):
+        lo, hi = None, None
+        for ef in EFS:
+            if fixed(ef)["recall@10"] >= target:
+                hi = ef
+                break
+            lo = ef
+        if hi is None:
+            rows.append({"target": target, "fixed": None, "learned_stop": None})
+            continue
+        if lo is not None:
+            for ef in range(lo + 8, hi, 8):
+                if fixed(ef)["recall@10"] >= target:
+                    hi = ef
+                    break
+        fx = fixed(hi)
+        best = None
+        for ls_ef in dict.fromkeys((hi, next((x for x in EFS if x > hi), hi))):
+            with torch.cuda.stream(stream):
+                feat, lab = learned_stop.collect(idx, Qtrain, gtrain, k, ls_ef, t_min, 4)
+                bits = learned_stop.export(learned_stop.train(feat, lab, epochs=6))
+                for te in (4, 8):
+                    # theta is picked on held-out queries with a margin of a tenth of the missing recall
+                    got = learned_stop.pick_theta(idx, Qth, gth, bits, k, ls_ef, t_min, te,
+                                                  target=target + 0.1 * (1.0 - target))
+                    if got is None:
+                        continue
+                    ids, _, st, _ = idx.search_stop(Qs, k, ls_ef, bits, theta=got[0], t_min=t_min, t_every=te,
+                                                    stats=True)
+                    rec = synth.recall(ids.cpu().numpy(), gt, k)
+                    q = rate(lambda: idx.search_stop(Qs, k, ls_ef, bits, theta=got[0], t_min=t_min, t_every=te))
+                    row = {"ef": ls_ef, "t_every": te, "theta": got[0], "recall@10": round(rec, 4),
+                           "qps": round(q, 1), "mean_expansions": round(st[:, 0].float().mean().item(), 2),
+                           "trace_points": int(feat.shape[0])}
+                    log(f"[ls-study] target {target} learned stop: {row}")
+                    if rec >= target and (best is None or q > best["qps"]):
+                        best = row
+        rows.append({"target": target, "fixed": fx, "learned_stop": best,
+                     "speedup": round(best["qps"] / fx["qps"], 3) if best else None})
+    wl = ("SIFT-shaped 1M x 128" if c == synth.SIFT_LIKE else
+          "1M x 768 unit-norm rank-128 + noise, queries from a mean-shifted copy")
+    print(json.dumps({"study": "learned stop vs fixed ef", "workload": wl + ", R=32 k-NN + random links, "
+                      f"{len(Q)} queries, k=10",
+                      "n_gpus": 1, "steps": args.steps, "train_queries": 16_000, "theta_queries": 4_000,
+                      "rows": rows}), flush=True)
 
 
 if __name__ == "__main__":

@@ -120,10 +120,10 @@ def gen_data(cfg: int, n: int | None = None, nq: int | None = None, D: int | Non
         return draw(g, n), draw(gq, nq)
     if cfg == 4:
         U = (g.standard_normal((D, 128)) / math.sqrt(D)).astype(f32)
+        gvec = g.standard_normal(128)  # the query shift is part of the distribution, not of one query draw
+        shift = (0.5 * math.sqrt(128) * gvec / np.linalg.norm(gvec)).astype(f32)
         X = chunked(n, lambda b: _normalize(g.standard_normal((b, 128), dtype=f32) @ U.T
                                             + f32(0.06) * g.standard_normal((b, D), dtype=f32)))
-        gvec = gq.standard_normal(128)
-        shift = (0.5 * math.sqrt(128) * gvec / np.linalg.norm(gvec)).astype(f32)
         Q = chunked(nq, lambda b: _normalize((gq.standard_normal((b, 128), dtype=f32) + shift) @ U.T
                                              + f32(0.06) * gq.standard_normal((b, D), dtype=f32)))
         return X, Q
