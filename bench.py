@@ -547,13 +547,15 @@ def ls_study(args, dev):
     cache = {}
 
     def fixed(ef):
+        """Recall and rate of the fixed beam ef, in the launch shape the autotuner picks for it."""
         if ef not in cache:
             with torch.cuda.stream(stream):
+                shape = idx.autotune(Qs, k, ef)[:3]
                 ids, _, st = idx.search(Qs, k, ef, stats=True)
                 rec = synth.recall(ids.cpu().numpy(), gt, k)
                 q = rate(lambda: idx.search(Qs, k, ef))
             cache[ef] = {"ef": ef, "recall@10": round(rec, 4), "qps": round(q, 1),
-                         "mean_expansions": round(st[:, 0].float().mean().item(), 2)}
+                         "mean_expansions": round(st[:, 0].float().mean().item(), 2), "launch": list(shape)}
             log(f"[ls-study] fixed ef={ef}: {cache[ef]}")
         return cache[ef]
 
@@ -576,6 +578,10 @@ def ls_study(args, dev):
         fx = fixed(hi)
         best = None
         for ls_ef in dict.fromkeys((hi, next((x for x in EFS if x > hi), hi))):
+            # the stop kernels use 8 wavefronts per workgroup and no residency cap; the hash
+            # factor is the one the autotuner picked for the fixed beam of the same size
+            shape = fixed(ls_ef)["launch"]
+            idx.set_launch(shape[0], shape[1], 0)
             with torch.cuda.stream(stream):
                 feat, lab = learned_stop.collect(idx, Qtrain, gtrain, k, ls_ef, t_min, 4)
                 bits = learned_stop.export(learned_stop.train(feat, lab, epochs=6))
