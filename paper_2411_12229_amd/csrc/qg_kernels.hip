@@ -2,8 +2,9 @@
 //
 //  rotate_kernel  : Y = X M^T on the matrix cores (fp64 MFMA 16x16x4, k ascending).
 //  encode_kernel  : RaBitQ codes and factors of every edge, one wavefront per vertex.
-//  search_kernel  : Algorithm 1, one query per wavefront; LUT, beam, visited
-//                   hash and top-k live in LDS, vertex blocks stream from HBM.
+//  search_kernel  : Algorithm 1, one query per wavefront; LUT, beam and visited
+//                   hash live in LDS, the top-k in registers (k <= 64) or LDS,
+//                   vertex blocks stream from HBM.
 //  estimate_kernel: the estimator alone for (query, vertex) pairs.
 //
 // Compiled with -ffp-contract=off: every fused multiply-add below is explicit.
