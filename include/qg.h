@@ -188,7 +188,9 @@ int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_wa
  * that slot's stream.  Batches grow with the load, short searches never wait
  * in a batch for long ones, and the slots overlap transfers with searches.  Every request's results are those of qg_search_ex
  * for that query alone with its own k and ef.  The index must outlive the
- * server; 1 <= streams <= 16, 1 <= k_max <= QG_MAX_K, 1 <= ef_max <= QG_MAX_EF. */
+ * server; 1 <= streams <= 16, 1 <= k_max <= QG_MAX_K, 1 <= ef_max <= QG_MAX_EF.
+ * Creation runs one single-query search on every slot (synchronously) so
+ * that the kernels are loaded before the first request. */
 typedef struct qg_server qg_server;
 
 int qg_server_create(qg_index *idx, int32_t streams, int32_t max_batch, int32_t k_max, int32_t ef_max,
@@ -201,15 +203,18 @@ int qg_server_submit(qg_server *s, const float *query, int32_t k, int32_t ef, ui
 
 /* Move up to max_results finished requests out of the server, oldest first.
  * Host outputs, each nullable: tags[n], ids[n][k_max] and dists[n][k_max]
- * (a request's k results, then (-1, +inf)), latency_s[n] (submission to
- * completion seen by the worker, seconds).  Returns the number written, or a
- * negative QG_* code. */
+ * (a request's k results, then (-1, +inf)), latency_s[n] (submission, or
+ * for a replayed request its scheduled arrival, to completion seen by the
+ * worker, seconds).  Returns the number written, or a negative QG_* code. */
 int64_t qg_server_poll(qg_server *s, int64_t max_results, uint64_t *tags, int32_t *ids, float *dists,
                        double *latency_s);
 
 /* Submit queries[n][d] (host) with tags 0 .. n-1 at arrival_s[i] seconds after
- * the call (an open-loop arrival trace), from a thread of the server; returns
- * at once.  The arrays must stay valid until qg_server_drain returns. */
+ * the call (an open-loop arrival trace; arrival_s non-decreasing), from a
+ * thread of the server; returns at once.  A request's latency counts from its
+ * scheduled arrival time, also when the thread queues it later (every request
+ * whose time has passed is queued at once).  The arrays must stay valid until
+ * qg_server_drain returns. */
 int qg_server_replay(qg_server *s, const float *queries, const int32_t *k, const int32_t *ef,
                      const double *arrival_s, int64_t n);
 

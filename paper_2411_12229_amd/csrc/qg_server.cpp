@@ -129,7 +129,16 @@ bool init_slot(qg_server* sv, Slot& s) {
   s.view = qgi::make_view(sv->idx);
   if (!s.view) return false;
   if (qg_set_stream(s.view, s.stream) != QG_OK || qg_reserve(s.view, sv->max_batch) != QG_OK) return false;
-  return true;
+  // one single-query search (a zero query, k = 1, ef = 1) so that the
+  // kernels are loaded before the first request arrives
+  std::memset(s.h_q, 0, sizeof(float) * D);
+  s.h_k[0] = 1;
+  s.h_ef[0] = 1;
+  return hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * D, hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+         hipMemcpyAsync(s.d_k, s.h_k, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+         hipMemcpyAsync(s.d_ef, s.h_ef, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+         qg_search_mixed(s.view, s.d_q, 1, s.d_k, s.d_ef, sv->k_max, 1, 0, s.d_ids, s.d_dists, nullptr) == QG_OK &&
+         hipStreamSynchronize(s.stream) == hipSuccess;
 }
 
 void fail_server(qg_server* sv, const std::string& msg) {
@@ -359,15 +368,44 @@ int qg_server_replay(qg_server* sv, const float* queries, const int32_t* k, cons
   if (!sv || n < 0 || (n > 0 && (!queries || !k || !ef || !arrival_s)))
     return qgi::set_error(QG_EINVAL, "bad replay arguments");
   if (sv->producer.joinable()) return qgi::set_error(QG_EINVAL, "a replay is already running");
-  for (int64_t i = 0; i < n; ++i)
+  for (int64_t i = 0; i < n; ++i) {
     if (k[i] < 1 || k[i] > sv->k_max || ef[i] < 1 || ef[i] > sv->ef_max)
       return qgi::set_error(QG_EINVAL, "k or ef outside the server's bounds");
+    if (i > 0 && !(arrival_s[i] >= arrival_s[i - 1])) return qgi::set_error(QG_EINVAL, "arrival times decrease");
+  }
   sv->producer = std::thread([sv, queries, k, ef, arrival_s, n]() {
+    // Open loop: request i enters at t0 + arrival_s[i], and its latency counts
+    // from that time even when the producer reaches it later.  Every request
+    // whose arrival time has passed is built outside the lock and queued
+    // under one lock, so the producer keeps up with high offered rates.
     const double t0 = now_s();
-    for (int64_t i = 0; i < n; ++i) {
-      while (now_s() - t0 < arrival_s[i]) {
-      }  // open loop: request i enters at its arrival time
-      if (qg_server_submit(sv, queries + (size_t)i * sv->D, k[i], ef[i], (uint64_t)i) != QG_OK) break;
+    std::vector<Request> rs;
+    for (int64_t i = 0; i < n;) {
+      const double t = now_s() - t0;
+      int64_t j = i;
+      while (j < n && arrival_s[j] <= t) ++j;
+      if (j == i) continue;  // spin until request i arrives
+      rs.resize((size_t)(j - i));
+      for (int64_t r = i; r < j; ++r) {
+        Request& q = rs[(size_t)(r - i)];
+        q.tag = (uint64_t)r;
+        q.k = k[r];
+        q.ef = ef[r];
+        q.t_submit = t0 + arrival_s[r];
+        q.q.assign(queries + (size_t)r * sv->D, queries + (size_t)(r + 1) * sv->D);
+      }
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->error != QG_OK || sv->stop) break;
+        for (auto& q : rs) {
+          const int c = ef_class(q.ef);
+          sv->pending[c].push_back(std::move(q));
+        }
+        sv->npending += j - i;
+        sv->submitted += j - i;
+      }
+      sv->cv.notify_one();
+      i = j;
     }
   });
   return QG_OK;

@@ -121,6 +121,8 @@ def test_server_argument_errors(cfg1):
             srv.submit(cfg1["Q"][0], 11, 32, 0)
         with pytest.raises(qg.QGError):
             srv.submit(cfg1["Q"][0], 5, 65, 0)
+        with pytest.raises(qg.QGError):  # arrival times must not decrease
+            srv.replay(cfg1["Q"][:2], np.array([5, 5]), np.array([32, 32]), np.array([0.002, 0.001]))
         srv.submit(cfg1["Q"][0], 5, 64, 7)
         srv.drain()
         tags, ids, _, _ = _collect(srv, 1)
