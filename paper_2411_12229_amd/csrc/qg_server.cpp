@@ -341,11 +341,22 @@ int qg_server_submit(qg_server* sv, const float* query, int32_t k, int32_t ef, u
 int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32_t* ids, float* dists,
                        double* latency_s) {
   if (!sv || max_results < 0) return qgi::set_error(QG_EINVAL, "server is NULL or max_results < 0");
-  std::lock_guard<std::mutex> lk(sv->mu);
+  // Finished batches are moved out under the lock and copied into the
+  // caller's arrays after it is released: first writes to fresh caller memory
+  // can take page faults, and the worker must not wait for them.
+  std::vector<DoneBatch> got;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    int64_t avail = 0;
+    while (avail < max_results && !sv->done.empty()) {
+      got.push_back(std::move(sv->done.front()));
+      sv->done.pop_front();
+      avail += (int64_t)(got.back().tags.size() - got.back().next);
+    }
+  }
   const size_t K = (size_t)sv->k_max;
   int64_t n = 0;
-  while (n < max_results && !sv->done.empty()) {
-    DoneBatch& b = sv->done.front();
+  for (auto& b : got) {
     while (n < max_results && b.next < b.tags.size()) {
       const size_t r = b.next++;
       if (tags) tags[n] = b.tags[r];
@@ -358,7 +369,11 @@ int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32
       }
       ++n;
     }
-    if (b.next == b.tags.size()) sv->done.pop_front();
+  }
+  // only the last batch taken can be partly handed out: its rest goes back in front
+  if (!got.empty() && got.back().next < got.back().tags.size()) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->done.push_front(std::move(got.back()));
   }
   return n;
 }
