@@ -212,7 +212,7 @@ def main():
             wpb_t, hf_t, cw_t, tms = idx.autotune(Qs, k, ef)
         shape = (wpb_t, hf_t, cw_t)
         tuned = {"waves_per_workgroup": wpb_t, "hash_factor": hf_t, "resident_waves_per_cu_cap": cw_t,
-                 "best_call_ms": round(tms, 4)}
+                 "median_call_ms": round(tms, 4)}
         log(f"[bench] autotune: {tuned}")
     qps, ms_per_step, kern_ms, rot_ms = timed(plain)
     expansions = int(s[:, 0].sum())

@@ -164,10 +164,11 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
  * wavefronts per compute unit against no cap (a batch only a little larger
  * than the resident query slots can finish sooner on fewer, less contended
  * slots).  The fastest setting is kept for later searches of this index.
+ * Each setting is timed as the median of seven calls after one untimed call.
  * Results do not depend on the choice, only the speed.  Outputs (host,
  * nullable): the chosen wavefronts per workgroup, F, the cap (0 = none) and
- * the best time in ms of one qg_search_ex call.  Synchronous; allocates and
- * frees temporary outputs. */
+ * the median time in ms of one qg_search_ex call in that setting.
+ * Synchronous; allocates and frees temporary outputs. */
 int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                 int32_t *out_wpb, int32_t *out_hash_factor, int32_t *out_cu_waves, double *out_ms);
 

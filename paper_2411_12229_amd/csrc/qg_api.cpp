@@ -559,19 +559,23 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
     cleanup();
     return fail(QG_ENOMEM, "autotune buffers");
   }
-  // one untimed call, then the best of three timed ones
+  // one untimed call, then the median of seven timed ones (the median, not the
+  // minimum: settings within a few percent of each other are told apart by
+  // their typical time, not by one lucky call)
   auto time_it = [&](double& t) {
     t = -1.0;
     if ((rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr))) return;
-    for (int rep = 0; rep < 3 && rc == QG_OK; ++rep) {
-      float ms = 0.0f;
+    float ms[7];
+    for (int rep = 0; rep < 7 && rc == QG_OK; ++rep) {
       if (hipEventRecord(e0, idx->stream) != hipSuccess) rc = fail(QG_EDEVICE, "hipEventRecord");
       if (!rc) rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr);
       if (!rc && (hipEventRecord(e1, idx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                  hipEventElapsedTime(&ms[rep], e0, e1) != hipSuccess))
         rc = fail(QG_EDEVICE, "timing events");
-      if (!rc && (t < 0 || ms < t)) t = ms;
     }
+    if (rc) return;
+    std::sort(ms, ms + 7);
+    t = ms[3];
   };
   // workgroup shape and hash size at full residency, then a cap on resident
   // wavefronts per compute unit for that shape (a batch only slightly larger
