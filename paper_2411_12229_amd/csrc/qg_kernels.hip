@@ -1019,7 +1019,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         if (live1 && np1 < ef) beam[np1] = e1;
       } else {
         const int ci = lanes_below(V);
-        for (int j = 0; j < nv4; ++j) sidx += cbuf[j] < cand;
+        for (int t = 0; t < nv4; t += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) sidx += cbuf[t + u] < cand;
+        }
         lbv = 0;
         for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {  // top down
           const int i = base + lane;
@@ -1028,11 +1031,16 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
           const uint64_t ke = e & ~(uint64_t)kChecked;
           const uint64_t Lm = ballot(live);
           int cnt = 0;
-          for (int j = 0; j < nv; ++j) {
-            const bool lt = cbuf[j] < ke;
-            cnt += lt;
-            const int le = __popcll(Lm & ~ballot(lt));
-            lbv += (ci == j) ? le : 0;
+          // four candidates per step, their words read together (the padding
+          // words compare below no entry and match no candidate's index)
+          for (int t = 0; t < nv4; t += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const bool lt = cbuf[t + u] < ke;
+              cnt += lt;
+              const int le = __popcll(Lm & ~ballot(lt));
+              lbv += (ci == t + u) ? le : 0;
+            }
           }
           const int np = i + cnt;
           const uint64_t tm = ballot(live && np == ef - 1);
@@ -1107,11 +1115,12 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // GV = false: main pass over all queries with the LDS visited hash.
 // GV = true : overflow pass over the queries the main pass handed over, with
 //             a global bitset per wavefront.
-// The stop-only kernels share one MLP image per workgroup of 8 wavefronts;
-// for the narrow shapes their registers are held to 80 so that LDS, not
-// registers, sets residency (6 wavefronts per SIMD).
+// The stop-only kernels share one MLP image per workgroup of 8 wavefronts.
+// For the narrow shapes the stop-only and mixed-batch kernels hold their
+// registers to 80, so that 6 wavefronts per SIMD fit (LDS sets residency for
+// the stop-only kernels anyway).
 template <int D, int R, bool GV, int LS>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LS == kLsStop && D <= 256 ? 6 : 1))) void search_kernel(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((LS == kLsStop || LS == kMixed) && D <= 256 ? 6 : 1))) void search_kernel(
     SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
