@@ -39,7 +39,9 @@ struct Request {
   uint64_t tag = 0;
   int32_t k = 0, ef = 0;
   double t_submit = 0;
-  std::vector<float> q;
+  std::vector<float> q;     // a copy of the query (submit)
+  const float* src = nullptr;  // or the caller's row, valid until drain (replay: no allocation per request)
+  const float* data() const { return src ? src : q.data(); }
 };
 
 // One finished batch: its rows are handed out by poll, oldest first.
@@ -129,8 +131,9 @@ bool init_slot(qg_server* sv, Slot& s) {
   s.view = qgi::make_view(sv->idx);
   if (!s.view) return false;
   if (qg_set_stream(s.view, s.stream) != QG_OK || qg_reserve(s.view, sv->max_batch) != QG_OK) return false;
-  // one single-query search (a zero query, k = 1, ef = 1) so that the
-  // kernels are loaded before the first request arrives
+  // one batch of a single zero query (k = 1, ef = 1) through every step a
+  // batch takes (uploads, search, downloads, event), so that kernels and copy
+  // paths are set up before the first request arrives
   std::memset(s.h_q, 0, sizeof(float) * D);
   s.h_k[0] = 1;
   s.h_ef[0] = 1;
@@ -138,7 +141,10 @@ bool init_slot(qg_server* sv, Slot& s) {
          hipMemcpyAsync(s.d_k, s.h_k, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
          hipMemcpyAsync(s.d_ef, s.h_ef, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
          qg_search_mixed(s.view, s.d_q, 1, s.d_k, s.d_ef, sv->k_max, 1, 0, s.d_ids, s.d_dists, nullptr) == QG_OK &&
-         hipStreamSynchronize(s.stream) == hipSuccess;
+         hipMemcpyAsync(s.h_ids, s.d_ids, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
+         hipMemcpyAsync(s.h_dists, s.d_dists, sizeof(float) * K, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
+         hipEventRecord(s.done, s.stream) == hipSuccess && hipEventSynchronize(s.done) == hipSuccess &&
+         hipEventQuery(s.done) == hipSuccess;
 }
 
 void fail_server(qg_server* sv, const std::string& msg) {
@@ -161,7 +167,7 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
   const int n = (int)take.size();
   const size_t D = (size_t)sv->D;
   for (int i = 0; i < n; ++i) {
-    std::memcpy(s.h_q + (size_t)i * D, take[i].q.data(), sizeof(float) * D);
+    std::memcpy(s.h_q + (size_t)i * D, take[i].data(), sizeof(float) * D);
     s.h_k[i] = take[i].k;
     s.h_ef[i] = take[i].ef;
   }
@@ -407,7 +413,7 @@ int qg_server_replay(qg_server* sv, const float* queries, const int32_t* k, cons
         q.k = k[r];
         q.ef = ef[r];
         q.t_submit = t0 + arrival_s[r];
-        q.q.assign(queries + (size_t)r * sv->D, queries + (size_t)(r + 1) * sv->D);
+        q.src = queries + (size_t)r * sv->D;
       }
       {
         std::lock_guard<std::mutex> lk(sv->mu);
