@@ -49,9 +49,10 @@ struct DoneBatch {
   std::vector<uint64_t> tags;
   std::vector<int32_t> ks;
   std::vector<double> latency;
-  std::vector<int32_t> ids;  // [n][k_max]
-  std::vector<float> dists;  // [n][k_max]
+  std::vector<int32_t> ids;  // row i's k_i results, rows back to back
+  std::vector<float> dists;
   size_t next = 0;           // rows already polled
+  size_t pos = 0;            // offset of row `next` in ids and dists
 };
 
 struct Slot {
@@ -86,6 +87,7 @@ struct qg_server {
   std::deque<Request> pending[kClasses];
   int64_t npending = 0;
   std::deque<DoneBatch> done;
+  std::vector<DoneBatch> spare;  // records already polled, kept for reuse (no allocation per batch)
   int64_t submitted = 0, completed = 0, batches = 0, largest = 0;
   int error = QG_OK;
   std::string errmsg;
@@ -216,17 +218,28 @@ void worker_loop(qg_server* sv) {
       }
       const double t = now_s();
       const size_t n = s.batch.size();
-      DoneBatch db;  // built outside the lock: one record per batch
+      DoneBatch db;  // built outside the lock: one record per batch, reusing a polled one's storage
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (!sv->spare.empty()) {
+          db = std::move(sv->spare.back());
+          sv->spare.pop_back();
+        }
+      }
+      db.next = db.pos = 0;
       db.tags.resize(n);
       db.ks.resize(n);
       db.latency.resize(n);
+      db.ids.clear();
+      db.dists.clear();
       for (size_t i = 0; i < n; ++i) {
         db.tags[i] = s.batch[i].tag;
         db.ks[i] = s.batch[i].k;
         db.latency[i] = t - s.batch[i].t_submit;
+        const size_t k = (size_t)s.batch[i].k;
+        db.ids.insert(db.ids.end(), s.h_ids + i * K, s.h_ids + i * K + k);
+        db.dists.insert(db.dists.end(), s.h_dists + i * K, s.h_dists + i * K + k);
       }
-      db.ids.assign(s.h_ids, s.h_ids + n * K);
-      db.dists.assign(s.h_dists, s.h_dists + n * K);
       s.batch.clear();
       s.busy = false;
       progressed = true;
@@ -370,16 +383,23 @@ int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32
       const size_t k = (size_t)b.ks[r];
       for (size_t j = 0; j < K; ++j) {
         const bool in = j < k;
-        if (ids) ids[n * K + j] = in ? b.ids[r * K + j] : -1;
-        if (dists) dists[n * K + j] = in ? b.dists[r * K + j] : __builtin_inff();
+        if (ids) ids[n * K + j] = in ? b.ids[b.pos + j] : -1;
+        if (dists) dists[n * K + j] = in ? b.dists[b.pos + j] : __builtin_inff();
       }
+      b.pos += k;
       ++n;
     }
   }
-  // only the last batch taken can be partly handed out: its rest goes back in front
-  if (!got.empty() && got.back().next < got.back().tags.size()) {
+  // only the last batch taken can be partly handed out: its rest goes back in
+  // front; the others keep their storage for later batches
+  if (!got.empty()) {
     std::lock_guard<std::mutex> lk(sv->mu);
-    sv->done.push_front(std::move(got.back()));
+    if (got.back().next < got.back().tags.size()) {
+      sv->done.push_front(std::move(got.back()));
+      got.pop_back();
+    }
+    for (auto& b : got)
+      if (sv->spare.size() < 64) sv->spare.push_back(std::move(b));
   }
   return n;
 }
