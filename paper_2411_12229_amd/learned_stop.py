@@ -88,13 +88,26 @@ def pick_theta(idx, queries: torch.Tensor, gt: torch.Tensor, mlp_bits: torch.Ten
                t_every: int, target: float, grid=None):
     """Largest stopping eagerness (smallest theta) whose recall on these queries reaches target.
     Returns (theta, recall, mean expansions) or None."""
-    best = None
-    for th in (grid if grid is not None else [6.0 - 0.25 * i for i in range(33)]):
+    def at(th):
         ids, _, st, _ = idx.search_stop(queries, k, ef, mlp_bits, theta=th, t_min=t_min, t_every=t_every,
                                         stats=True)
-        r = recall_rows(ids, gt).mean().item()
-        if r >= target:
-            best = (th, r, st[:, 0].float().mean().item())
-        else:
+        return th, recall_rows(ids, gt).mean().item(), st[:, 0].float().mean().item()
+
+    best, fail = None, None
+    for th in (grid if grid is not None else [6.0 - 0.25 * i for i in range(33)]):
+        got = at(th)
+        if got[1] < target:
+            fail = th
             break
+        best = got
+    # between the last theta that reaches the target and the first that does not,
+    # in steps of 0.05 (the default grid only)
+    if grid is None and best is not None and fail is not None:
+        th = best[0] - 0.05
+        while th > fail + 1e-9:
+            got = at(round(th, 2))
+            if got[1] < target:
+                break
+            best = got
+            th -= 0.05
     return best
