@@ -132,6 +132,15 @@ int qg_search_mixed(const qg_index *idx, const float *queries, int64_t nq, const
                     const int32_t *ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags, int32_t *out_ids,
                     float *out_dists, int32_t *out_stats);
 
+/* qg_search_mixed with the learned stop: every query runs with its own k_q
+ * and ef_q and the shared stop model (stop->mlp non-NULL, theta, t_min,
+ * t_every; stop->trace_max must be 0).  Each query's results are those of
+ * qg_search_stop for that query alone with its own k_q and ef_q.  QG_EINVAL
+ * without a model or with a trace requested. */
+int qg_search_mixed_stop(const qg_index *idx, const float *queries, int64_t nq, const int32_t *k_per_query,
+                         const int32_t *ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags,
+                         const qg_stop_params *stop, int32_t *out_ids, float *out_dists, int32_t *out_stats);
+
 /* out[n][d] = M in[n][d] for the index's rotation M (Eq. rotation), on the
  * matrix cores: fp64 products accumulated over j ascending, rounded once to
  * fp32.  This is the first step of qg_search, exposed for checking. */
@@ -196,6 +205,14 @@ typedef struct qg_server qg_server;
 
 int qg_server_create(qg_index *idx, int32_t streams, int32_t max_batch, int32_t k_max, int32_t ef_max,
                      qg_server **out);
+
+/* Run every later batch of this server with the learned stop (the model,
+ * theta, t_min and t_every of *stop, trace_max 0; the MLP parameters are
+ * device memory that must stay valid while the server runs), or without it
+ * (stop = NULL).  Each request's results are then those of qg_search_stop for
+ * that query alone with its own k and ef.  Call it while no request is
+ * waiting or in flight (after creation or qg_server_drain). */
+int qg_server_set_stop(qg_server *s, const qg_stop_params *stop);
 
 /* Queue one request: query[d] (fp32, host memory, copied before the call
  * returns), 1 <= k <= k_max, 1 <= ef <= ef_max, and a caller tag returned with

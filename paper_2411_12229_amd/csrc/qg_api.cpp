@@ -482,8 +482,9 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   a.overflow_list = idx->overflow;
   a.fb_bits = idx->fb_bits;
   a.fb_words = idx->fb_words;
-  // ls_mode 1: stop only, MLP in LDS; 2: trace (and the MLP, if given, read from global memory); 3: mixed batch
-  const int ls = ef_q ? 3 : !stop ? 0 : (stop->trace_max == 0 && stop->mlp ? 1 : 2);
+  // ls_mode 1: stop only, MLP in LDS; 2: trace (and the MLP, if given, read from global memory); 3: mixed
+  // batch; 4: mixed batch with the stop (MLP in LDS)
+  const int ls = ef_q ? (stop ? 4 : 3) : !stop ? 0 : (stop->trace_max == 0 && stop->mlp ? 1 : 2);
   if (stop) {
     a.ls_w = stop->mlp;
     a.ls_theta = stop->theta;
@@ -499,8 +500,9 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   const qgl::SearchLds L = qgl::search_lds(idx->D, idx->R, ef_cap, 1 << hbits, k_cap);
   const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
   const size_t lds_cap = 160 * 1024;
-  const size_t extra = ls == 1 ? qgk::mlp_lds_bytes() : 0;  // MLP image shared by a workgroup
-  int wpb = ls == 1 ? 8 : idx->wpb_pref;  // stop-only: 8 wavefronts share the MLP image
+  const bool mlp_lds = ls == 1 || ls == 4;
+  const size_t extra = mlp_lds ? qgk::mlp_lds_bytes() : 0;  // MLP image shared by a workgroup
+  int wpb = mlp_lds ? 8 : idx->wpb_pref;  // 8 wavefronts share the MLP image
   while (wpb > 1 && (size_t)wpb * L.total + extra > lds_cap) wpb >>= 1;
   if ((size_t)L.total + extra > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
   const size_t lds = (size_t)wpb * L.total + extra;
@@ -533,6 +535,16 @@ int qg_search_mixed(const qg_index* idx, const float* queries, int64_t nq, const
                     float* out_dists, int32_t* out_stats) {
   if (nq > 0 && (!k_per_query || !ef_per_query)) return fail(QG_EINVAL, "NULL per-query k or ef array");
   return search_impl(idx, queries, nq, k_max, ef_max, k_per_query, ef_per_query, flags, nullptr, out_ids, out_dists,
+                     out_stats);
+}
+
+int qg_search_mixed_stop(const qg_index* idx, const float* queries, int64_t nq, const int32_t* k_per_query,
+                         const int32_t* ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags,
+                         const qg_stop_params* stop, int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+  if (nq > 0 && (!k_per_query || !ef_per_query)) return fail(QG_EINVAL, "NULL per-query k or ef array");
+  if (!stop || !stop->mlp) return fail(QG_EINVAL, "a mixed batch with the stop needs the MLP parameters");
+  if (stop->trace_max != 0) return fail(QG_EINVAL, "a mixed batch records no trace");
+  return search_impl(idx, queries, nq, k_max, ef_max, k_per_query, ef_per_query, flags, stop, out_ids, out_dists,
                      out_stats);
 }
 

@@ -517,11 +517,16 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 // W2[64][64], b2[64], W3[64], b3.
 // learned-stop modes of the search kernels
 // Kernel modes: plain search, learned stop (MLP in LDS), learned stop with
-// trace, and per-query k / ef (a mixed batch).  Each is its own instantiation,
-// so the plain kernel carries none of the others' state.
-constexpr int kLsOff = 0, kLsStop = 1, kLsTrace = 2, kMixed = 3;
+// trace, per-query k / ef (a mixed batch), and a mixed batch with the learned
+// stop.  Each is its own instantiation, so the plain kernel carries none of the
+// others' state.
+constexpr int kLsOff = 0, kLsStop = 1, kLsTrace = 2, kMixed = 3, kMixedStop = 4;
 template <int LS>
-constexpr bool has_stop = LS == kLsStop || LS == kLsTrace;
+constexpr bool has_stop = LS == kLsStop || LS == kLsTrace || LS == kMixedStop;
+template <int LS>
+constexpr bool is_mixed = LS == kMixed || LS == kMixedStop;
+template <int LS>
+constexpr bool mlp_in_lds = LS == kLsStop || LS == kMixedStop;
 
 constexpr int kLsW1 = 0, kLsB1 = 64 * 16, kLsW2 = kLsB1 + 64, kLsB2 = kLsW2 + 64 * 64, kLsW3 = kLsB2 + 64,
               kLsB3 = kLsW3 + 64;
@@ -670,7 +675,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   constexpr uint64_t kNone = ~0ull;  // sorts after every real entry
   const int lane = lane_id();
   int ef = a.ef, k = a.k;
-  if constexpr (LS == kMixed) {
+  if constexpr (is_mixed<LS>) {
     // a beam size and result count of its own; a.ef and a.k are the bounds
     ef = uni(a.ef_q[q]);
     k = uni(a.k_q[q]);
@@ -1065,7 +1070,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         const float nnk = nn_in_regs ? rdlane(nrk, nnc - 1) : uni(nkey[nnc - 1]);
         F.compute(expansions, pops, nnc, k, since, de, nn1, nnk, bfk, size, ef, dp, app, R);
         float out;
-        if constexpr (LS == kLsStop)
+        if constexpr (mlp_in_lds<LS>)
           out = stop_mlp_lds(mlp, F.mine, lane, reinterpret_cast<float*>(lds + L.cand));
         else
           out = a.ls_w ? stop_mlp(a.ls_w, F, lane) : __builtin_nanf("");
@@ -1091,7 +1096,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   }
 
   // answer: NN ascending by (distance, id), padded with (-1, inf)
-  const int k_out = LS == kMixed ? a.k_out : k;  // a mixed batch's rows are k_out wide
+  const int k_out = is_mixed<LS> ? a.k_out : k;  // a mixed batch's rows are k_out wide
   for (int i = lane; i < k_out; i += 64) {
     int32_t id = -1;
     float d = __builtin_inff();
@@ -1120,7 +1125,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // registers to 80, so that 6 wavefronts per SIMD fit (LDS sets residency for
 // the stop-only kernels anyway).
 template <int D, int R, bool GV, int LS>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((LS == kLsStop || LS == kMixed) && D <= 256 ? 6 : 1))) void search_kernel(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((mlp_in_lds<LS> || LS == kMixed) && D <= 256 ? 6 : 1))) void search_kernel(
     SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
@@ -1128,7 +1133,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((LS == kLsS
   const qgl::SearchLds L = qgl::search_lds(D, R, a.ef_cap, GV ? 0 : (1 << a.hash_bits), a.k_cap);
   uint8_t* lds = smem + wave * L.total;
   uint8_t* mlp = smem + (blockDim.x >> 6) * L.total;  // after every wavefront's area
-  if constexpr (LS == kLsStop) {
+  if constexpr (mlp_in_lds<LS>) {
     stage_mlp(a.ls_w, mlp);
     __syncthreads();
   }
@@ -1235,6 +1240,7 @@ hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const Se
     case kLsStop: return launch_search_t<d, r, gv, kLsStop>(a, grid, wpb, lds, st);   \
     case kLsTrace: return launch_search_t<d, r, gv, kLsTrace>(a, grid, wpb, lds, st); \
     case kMixed: return launch_search_t<d, r, gv, kMixed>(a, grid, wpb, lds, st);     \
+    case kMixedStop: return launch_search_t<d, r, gv, kMixedStop>(a, grid, wpb, lds, st); \
     default: return hipErrorInvalidValue;                                           \
   }
 #define QG_CASE(d, r)                  \
@@ -1255,6 +1261,7 @@ int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, siz
     case kLsStop: return occupancy_t<d, r, gv, kLsStop>(wpb, lds);          \
     case kLsTrace: return occupancy_t<d, r, gv, kLsTrace>(wpb, lds);        \
     case kMixed: return occupancy_t<d, r, gv, kMixed>(wpb, lds);            \
+    case kMixedStop: return occupancy_t<d, r, gv, kMixedStop>(wpb, lds);    \
     default: return 0;                                                    \
   }
 #define QG_CASE(d, r)                  \

@@ -88,6 +88,8 @@ struct qg_server {
   int64_t npending = 0;
   std::deque<DoneBatch> done;
   std::vector<DoneBatch> spare;  // records already polled, kept for reuse (no allocation per batch)
+  bool use_stop = false;         // batches run with the learned stop (qg_server_set_stop)
+  qg_stop_params stop_params{};
   int64_t submitted = 0, completed = 0, batches = 0, largest = 0;
   int error = QG_OK;
   std::string errmsg;
@@ -182,8 +184,11 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
   }
   int32_t ef_batch = 1;
   for (int i = 0; i < n; ++i) ef_batch = std::max(ef_batch, take[i].ef);
-  if (qg_search_mixed(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, ef_batch, 0, s.d_ids, s.d_dists, nullptr) !=
-      QG_OK) {
+  const int rc = sv->use_stop ? qg_search_mixed_stop(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, ef_batch, 0,
+                                                     &sv->stop_params, s.d_ids, s.d_dists, nullptr)
+                              : qg_search_mixed(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, ef_batch, 0, s.d_ids,
+                                                s.d_dists, nullptr);
+  if (rc != QG_OK) {
     fail_server(sv, std::string("search: ") + qg_last_error());
     return false;
   }
@@ -332,6 +337,18 @@ int qg_server_create(qg_index* idx, int32_t streams, int32_t max_batch, int32_t 
   }
   sv->worker = std::thread(worker_loop, sv);
   *out = sv;
+  return QG_OK;
+}
+
+int qg_server_set_stop(qg_server* sv, const qg_stop_params* stop) {
+  if (!sv) return qgi::set_error(QG_EINVAL, "server is NULL");
+  if (stop && (!stop->mlp || stop->trace_max != 0 || stop->t_min < 1 || stop->t_every < 1))
+    return qgi::set_error(QG_EINVAL, "the stop needs the MLP parameters, t_min, t_every >= 1 and no trace");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->npending > 0 || sv->completed < sv->submitted)
+    return qgi::set_error(QG_EINVAL, "requests are waiting or in flight");
+  sv->use_stop = stop != nullptr;
+  if (stop) sv->stop_params = *stop;
   return QG_OK;
 }
 

@@ -55,6 +55,7 @@ def _load():
         "qg_search_ex": ([P, P, i64, i32, i32, i32, P, P, P], c_int),
         "qg_search_stop": ([P, P, i64, i32, i32, i32, ctypes.POINTER(StopParams), P, P, P], c_int),
         "qg_search_mixed": ([P, P, i64, P, P, i32, i32, i32, P, P, P], c_int),
+        "qg_search_mixed_stop": ([P, P, i64, P, P, i32, i32, i32, ctypes.POINTER(StopParams), P, P, P], c_int),
         "qg_rotate": ([P, P, i64, P], c_int),
         "qg_estimate": ([P, P, P, i64, P, P, P], c_int),
         "qg_copy_blocks": ([P, i64, i64, P], c_int),
@@ -72,6 +73,7 @@ def _load():
         "qg_server_submit": ([P, P, i32, i32, ctypes.c_uint64], c_int),
         "qg_server_poll": ([P, i64, P, P, P, P], i64),
         "qg_server_replay": ([P, P, P, P, P, i64], c_int),
+        "qg_server_set_stop": ([P, ctypes.POINTER(StopParams)], c_int),
         "qg_server_drain": ([P, ctypes.c_double], c_int),
         "qg_server_stats": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
                             c_int),
@@ -164,6 +166,29 @@ class Index:
         dists = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
         st = torch.empty((nq, 4), dtype=torch.int32, device=dev) if stats else None
         qg_search_mixed(self, queries, nq, k, ef, k_max, ef_max, flags, ids, dists, st)
+        return (ids, dists, st) if stats else (ids, dists)
+
+    def search_mixed_stop(self, queries: torch.Tensor, k: torch.Tensor, ef: torch.Tensor, mlp: torch.Tensor,
+                          theta: float, t_min: int = 8, t_every: int = 4, k_max: int | None = None,
+                          ef_max: int | None = None, flags: int = 0, stats: bool = False):
+        """search_mixed with the learned stop (shared model, theta, t_min, t_every; no trace)."""
+        nq = queries.shape[0]
+        dev = queries.device
+        if k_max is None:
+            k_max = int(k.max().item()) if nq else 1
+        if ef_max is None:
+            ef_max = int(ef.max().item()) if nq else 1
+        if queries.shape != (nq, self.d) or k.shape != (nq,) or ef.shape != (nq,):
+            raise ValueError("shape mismatch")
+        ids = torch.empty((nq, k_max), dtype=torch.int32, device=dev)
+        dists = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=dev) if stats else None
+        sp = _stop_params(mlp, theta, t_min, t_every)
+        _check(_lib.qg_search_mixed_stop(self._h, _dev(queries, torch.float32, "queries"), nq,
+                                         _dev(k, torch.int32, "k_per_query"), _dev(ef, torch.int32, "ef_per_query"),
+                                         k_max, ef_max, flags, ctypes.byref(sp), _dev(ids, torch.int32, "out_ids"),
+                                         _dev(dists, torch.float32, "out_dists"),
+                                         _dev(st, torch.int32, "out_stats") if stats else None))
         return (ids, dists, st) if stats else (ids, dists)
 
     def search(self, queries: torch.Tensor, k: int, ef: int, flags: int = 0, stats: bool = False):
@@ -287,6 +312,16 @@ def qg_search_mixed(idx: Index, queries, nq: int, k_per_query, ef_per_query, k_m
                                 st))
 
 
+def _stop_params(mlp, theta: float, t_min: int, t_every: int) -> StopParams:
+    """Stop parameters without a trace (the MLP kept alive by the caller)."""
+    if mlp is None or mlp.numel() != QG_STOP_MLP_PARAMS or mlp.element_size() != 2:
+        raise ValueError("MLP parameters must be QG_STOP_MLP_PARAMS 16-bit values")
+    sp = StopParams()
+    sp.mlp = _dev(mlp, mlp.dtype, "mlp")
+    sp.theta, sp.t_min, sp.t_every, sp.trace_max = float(theta), int(t_min), int(t_every), 0
+    return sp
+
+
 def qg_search_stop(idx: Index, queries, nq: int, k: int, ef: int, flags: int, mlp, theta: float, t_min: int,
                    t_every: int, trace_max: int, trace, out_ids, out_dists, out_stats=None):
     if queries.shape != (nq, idx.d) or out_ids.shape != (nq, k) or out_dists.shape != (nq, k):
@@ -372,6 +407,17 @@ class Server:
         _check(_lib.qg_server_create(index.handle, streams, max_batch, k_max, ef_max, ctypes.byref(h)))
         self._h, self._index, self.d, self.k_max = h, index, index.d, k_max
         self._replay = None
+        self._stop = None
+
+    def set_stop(self, mlp: torch.Tensor | None, theta: float = 0.0, t_min: int = 8, t_every: int = 4) -> None:
+        """Run later batches with the learned stop (mlp: bf16 bits on the device), or without it (None)."""
+        if mlp is None:
+            _check(_lib.qg_server_set_stop(self._h, None))
+            self._stop = None
+            return
+        sp = _stop_params(mlp, theta, t_min, t_every)
+        _check(_lib.qg_server_set_stop(self._h, ctypes.byref(sp)))
+        self._stop = mlp  # the server reads the parameters from device memory while it runs
 
     def submit(self, query: np.ndarray, k: int, ef: int, tag: int) -> None:
         q = np.ascontiguousarray(query, dtype=np.float32).reshape(-1)

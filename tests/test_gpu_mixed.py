@@ -69,6 +69,56 @@ def test_mixed_batch_equals_oracle_per_query(cfg1, seed, nq):
     assert np.array_equal(gs[:, :3], os_[:, :3])
 
 
+def _stop_model(c, seed=5, t_min=4, t_every=2):
+    """A random bf16 stop model and a theta at which about a third of the evaluation points stop."""
+    rng = np.random.default_rng(seed)
+    w = ((rng.standard_normal(oracle.LS_PARAMS) * 0.3).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    _, _, _, (_, _, oo, oc) = oracle.search_ls(c["blocks"], 128, 32, c["e"], c["M"], c["Q"][:64], 10, 64, w=w,
+                                               theta=np.inf, t_min=t_min, t_every=t_every, max_evals=128)
+    outs = np.concatenate([oo[i, :oc[i]] for i in range(len(oc))])
+    return w, float(np.quantile(outs, 0.7))
+
+
+def test_mixed_stop_equals_oracle_per_query(cfg1):
+    """A mixed batch with the learned stop: every query equals the oracle's
+    stopped search for that query with its own k and ef (shared model, theta,
+    t_min and t_every)."""
+    c = cfg1
+    rng = np.random.default_rng(7)
+    nq = 150
+    Q = c["Q"][:nq]
+    ks = rng.choice([1, 10, 33], nq).astype(np.int32)
+    efs = rng.choice([16, 64, 160], nq).astype(np.int32)
+    w, theta = _stop_model(c)
+    wd = torch.from_numpy(w.view(np.int16)).to(DEV)
+    ids, d, st = c["idx"].search_mixed_stop(T(Q), T(ks), T(efs), wd, theta, t_min=4, t_every=2, k_max=33,
+                                            ef_max=160, stats=True)
+    torch.cuda.synchronize()
+    gi, gd, gs = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    stopped = 0
+    for k, ef in sorted(set(zip(ks.tolist(), efs.tolist()))):
+        sel = np.nonzero((ks == k) & (efs == ef))[0]
+        oi, od, os_, _ = oracle.search_ls(c["blocks"], 128, 32, c["e"], c["M"], Q[sel], k, ef, w=w, theta=theta,
+                                          t_min=4, t_every=2)
+        assert np.array_equal(gi[sel, :k], oi) and np.array_equal(gd[sel, :k], od), f"k={k} ef={ef}"
+        assert np.array_equal(gs[sel, :3], os_[:, :3]), f"counters k={k} ef={ef}"
+        assert (gi[sel, k:] == -1).all()
+        full = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], Q[sel], k, ef, with_stats=True)[2]
+        stopped += int((os_[:, 0] < full[:, 0]).sum())
+    assert stopped > 0, "theta stopped no query early"
+
+
+def test_mixed_stop_argument_errors(cfg1):
+    c = cfg1
+    Qd = T(c["Q"][:4])
+    k = T(np.full(4, 10, np.int32))
+    ef = T(np.full(4, 64, np.int32))
+    with pytest.raises(ValueError):
+        c["idx"].search_mixed_stop(Qd, k, ef, None, 0.0)
+    lib = qg.lib()
+    assert lib.qg_search_mixed_stop(c["idx"].handle, None, 0, None, None, 10, 10, 0, None, None, None, None) == -1
+
+
 def test_mixed_uniform_equals_plain_search(cfg1):
     c = cfg1
     Qd = T(c["Q"])

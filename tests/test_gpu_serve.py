@@ -6,6 +6,8 @@ with its own k and ef (ids and distances bit-equal, which the oracle also
 returns); every tag comes back exactly once; a timed open-loop trace reports
 sane latencies.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -110,6 +112,38 @@ def test_replay_open_loop_trace(cfg1):
         sel = np.nonzero((ks[tags] == k) & (efs[tags] == ef))[0]
         gi, gd = c["idx"].search(T(Q[tags[sel]]), k, ef)
         assert np.array_equal(ids[sel, :k], gi.cpu().numpy()) and np.array_equal(dists[sel, :k], gd.cpu().numpy())
+
+
+def test_server_with_learned_stop(cfg1):
+    """With qg_server_set_stop every result equals that query searched alone
+    with the learned stop at its own k and ef."""
+    c = cfg1
+    rng = np.random.default_rng(21)
+    w = ((rng.standard_normal(qg.QG_STOP_MLP_PARAMS) * 0.3).astype(np.float32).view(np.uint32) >> 16)
+    wd = torch.from_numpy(w.astype(np.uint16).view(np.int16)).to(DEV)
+    theta = 0.5
+    n = 300
+    sel = rng.integers(0, len(c["Q"]), n)
+    ks = rng.choice([1, 10], n).astype(np.int32)
+    efs = rng.choice([32, 96], n).astype(np.int32)
+    srv = qg.Server(c["idx"], streams=2, max_batch=64, k_max=10, ef_max=96)
+    try:
+        sp = qg.StopParams()  # no model: refused
+        sp.t_min, sp.t_every = 4, 2
+        assert qg.lib().qg_server_set_stop(srv._h, ctypes.byref(sp)) == qg.QG_EINVAL
+        srv.set_stop(wd, theta, t_min=4, t_every=2)
+        for i in range(n):
+            srv.submit(c["Q"][sel[i]], int(ks[i]), int(efs[i]), i)
+        srv.drain()
+        tags, ids, dists, _ = _collect(srv, n)
+    finally:
+        srv.close()
+    for k, ef in ((1, 32), (1, 96), (10, 32), (10, 96)):
+        rows = np.nonzero((ks[tags] == k) & (efs[tags] == ef))[0]
+        if rows.size == 0:
+            continue
+        gi, gd, _, _ = c["idx"].search_stop(T(c["Q"][sel[tags[rows]]]), k, ef, wd, theta=theta, t_min=4, t_every=2)
+        assert np.array_equal(ids[rows, :k], gi.cpu().numpy()) and np.array_equal(dists[rows, :k], gd.cpu().numpy())
 
 
 def test_server_argument_errors(cfg1):
