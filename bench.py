@@ -405,7 +405,10 @@ def main():
         idx.set_launch(shape[0], shape[1], 0)  # batches of every size: no residency cap
         rng = np.random.default_rng(11)
         ef_classes = (max(ef // 2, 1), ef, 4 * ef)
-        for rate in (50_000, 200_000, 1_000_000, 4_000_000):
+        legs = [(r, False) for r in (50_000, 200_000, 1_000_000, 4_000_000)]
+        if ls_res is not None:
+            legs.append((1_000_000, True))  # the same trace shape with the learned stop in every batch
+        for rate, with_stop in legs:
             n = int(min(rate * 0.4, 400_000))
             qsel = rng.integers(0, args.nq, n)
             ks = rng.choice([1, 10, 100], n).astype(np.int32)
@@ -413,6 +416,8 @@ def main():
             arrival = np.cumsum(rng.exponential(1.0 / rate, n))
             srv = qg.Server(idx, streams=3, max_batch=8192, k_max=100, ef_max=max(ef_classes))
             try:
+                if with_stop:
+                    srv.set_stop(bits, ls_res["theta"], t_min=ls_res["t_min"], t_every=ls_res["t_every"])
                 # latencies are taken by the server when each batch completes; results are
                 # collected after the trace (a Python loop polling during the trace stalled
                 # the server threads once for ~5 ms per run, a harness effect)
@@ -430,7 +435,8 @@ def main():
                 srv.close()
             lat = np.concatenate(lat)
             p50, p99 = np.percentile(lat, [50, 99])
-            row = {"offered_per_s": rate, "requests": n, "completed_per_s": round(n / wall, 1),
+            row = {"offered_per_s": rate, "learned_stop": with_stop, "requests": n,
+                   "completed_per_s": round(n / wall, 1),
                    "p50_ms": round(p50 * 1e3, 3), "p99_ms": round(p99 * 1e3, 3), "batches": st["batches"],
                    "mean_batch": round(n / max(st["batches"], 1), 1), "largest_batch": st["largest_batch"]}
             serving.append(row)
@@ -492,7 +498,9 @@ def main():
         "end_to_end_qps_with_pcie": round(e2e_qps, 1),
         "serving": {"workload": f"single queries from the {args.nq} benchmark queries, open-loop Poisson arrivals, "
                                 f"k ~ U{{1,10,100}}, ef ~ U{{{max(ef // 2, 1)},{ef},{4 * ef}}}, 3 streams, "
-                                "batches up to 8192", "rates": serving} if serving is not None else None,
+                                "batches up to 8192; the row with learned_stop true runs every batch with the "
+                                "bench's learned-stop model and theta", "rates": serving}
+        if serving is not None else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,
