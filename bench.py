@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--launch", default="",
                     help="wpb,hash_factor,cu_waves: set this launch shape for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the w/o ME leg")
     ap.add_argument("--ls-study", action="store_true",
                     help="instead of the benchmark line: learned stop against fixed ef at recall@10 0.90 / 0.95 / "
                          "0.99 (one JSON line)")
@@ -150,7 +151,7 @@ def main():
         for _ in range(3):
             run(ef)
         qps = 3 * args.nq / (time.time() - t1)
-        sweep.append({"ef": ef, "recall@10": round(rec, 4), "qps_host_clock": round(qps), "mean_expansions":
+        sweep.append({"ef": ef, "recall@10": round(rec, 4) if gt is not None else None, "qps_host_clock": round(qps), "mean_expansions":
                       round(float(s[:, 0].mean()), 2), "max_expansions": int(s[:, 0].max()),
                       "overflow_queries": int(s[:, 3].sum())})
         log(f"[bench] ef={ef:4d} recall@10={rec:.4f} E_q mean {s[:, 0].mean():.1f} max {s[:, 0].max()} "
@@ -222,8 +223,32 @@ def main():
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4), "traffic": None,
                 "bytes_per_launch": alg_bytes, "expansions_per_launch": expansions,
                 "block_bytes": idx.block_bytes, "kernel_ms": round(kern_ms, 4), "rotate_kernel_ms": round(rot_ms, 4)}
-    fixed = {"ef": ef, "recall@10": round(rec, 4), "qps": round(qps, 1), "ms_per_step": round(ms_per_step, 4),
+    fixed = {"ef": ef, "recall@10": round(rec, 4) if gt is not None else None, "qps": round(qps, 1), "ms_per_step": round(ms_per_step, 4),
              "mean_expansions": round(expansions / args.nq, 2), "autotune": tuned}
+
+    # the "w/o ME" ablation (Sec. 4.2.3): a vertex enters the beam only on its
+    # first estimate; recall and rate against the beam size, beside the sweep
+    no_me = None
+    if not args.no_ablation and gt is not None:
+        no_me = []
+        for ef_a in sorted({16, 32, 48, 64, ef, 96, 128, 192}):
+            with torch.cuda.stream(stream):
+                ids_a, _, st_a = idx.search(Qs, k, ef_a, flags=qg.QG_SEARCH_NO_ME, stats=True)
+            stream.synchronize()
+            rec_a = synth.recall(ids_a.cpu().numpy(), gt, k)
+            sa = st_a.cpu().numpy()
+            t1 = time.time()
+            with torch.cuda.stream(stream):
+                for _ in range(3):
+                    idx.search(Qs, k, ef_a, flags=qg.QG_SEARCH_NO_ME)
+            stream.synchronize()
+            qps_a = 3 * args.nq / (time.time() - t1)
+            no_me.append({"ef": ef_a, "recall@10": round(rec_a, 4), "qps_host_clock": round(qps_a),
+                          "mean_expansions": round(float(sa[:, 0].mean()), 2),
+                          "mean_appended": round(float(sa[:, 2].mean()), 2),
+                          "overflow_queries": int(sa[:, 3].sum())})
+            log(f"[bench] w/o ME ef={ef_a:4d} recall@10={rec_a:.4f} E_q mean {sa[:, 0].mean():.1f} "
+                f"~{qps_a:,.0f} q/s")
 
     # learned stop: trained on separately seeded queries, theta picked on a held-out part of them
     ls_res = None
@@ -504,6 +529,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "without_me": {"what": "the w/o ME ablation of Sec. 4.2.3 on the same index and queries, same launch shape; "
+                               "compare with sweep (multiple estimates)", "sweep": no_me} if no_me else None,
     }
     print(json.dumps(out), flush=True)
 

@@ -45,7 +45,8 @@ enum {
 
 /* Flags for qg_search_ex. */
 enum {
-  QG_SEARCH_NO_ME = 1,     /* "w/o ME" ablation (Sec. 4.2.3): a vertex enters the beam only on its first estimate */
+  QG_SEARCH_NO_ME = 1,     /* "w/o ME" ablation (Sec. 4.2.3): a vertex enters the beam only on its first estimate
+                              (plain search only: QG_EUNSUPPORTED with per-query k and ef or the learned stop) */
   QG_SEARCH_SMALL_HASH = 2 /* test hook: shrink the on-chip visited set to 128 slots so that queries take the
                               overflow path (results are identical by construction) */
 };

@@ -437,7 +437,8 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   if (k <= 0 || ef <= 0) return fail(QG_EINVAL, "k and ef must be positive");
   if (k > QG_MAX_K || ef > QG_MAX_EF) return fail(QG_EUNSUPPORTED, "k or ef above the supported maximum");
   if (flags & ~(QG_SEARCH_NO_ME | QG_SEARCH_SMALL_HASH)) return fail(QG_EINVAL, "unknown flags");
-  if (flags & QG_SEARCH_NO_ME) return fail(QG_EUNSUPPORTED, "QG_SEARCH_NO_ME is not supported on the device");
+  const bool no_me = flags & QG_SEARCH_NO_ME;
+  if (no_me && (ef_q || stop)) return fail(QG_EUNSUPPORTED, "QG_SEARCH_NO_ME applies to the plain search only");
   if (stop) {
     if (stop->t_min < 1 || stop->t_every < 1 || stop->trace_max < 0) return fail(QG_EINVAL, "bad stop parameters");
     if (stop->trace_max > 0 && (!stop->trace_features || !stop->trace_nn || !stop->trace_out || !stop->trace_count))
@@ -456,7 +457,12 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   // visited hash: 2^h >= 3 ef slots (at least 256), filled to at most one half;
   // queries that visit more finish in the overflow pass
   int hbits = 8;
-  while ((1 << hbits) < idx->hash_factor * ef && hbits < 14) ++hbits;
+  // w/o ME the set holds every estimated vertex, not only the visited ones: up
+  // to R per expansion (measured: about two thirds of them new), for about ef
+  // expansions
+  const int64_t hash_want =
+      no_me ? (int64_t)idx->hash_factor * idx->R * (ef + 16) / 2 : (int64_t)idx->hash_factor * ef;
+  while ((1 << hbits) < hash_want && hbits < 14) ++hbits;
   if (flags & QG_SEARCH_SMALL_HASH) hbits = 7;
   qgk::SearchArgs a{};
   a.blocks = idx->blocks;
@@ -483,8 +489,8 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   a.fb_bits = idx->fb_bits;
   a.fb_words = idx->fb_words;
   // ls_mode 1: stop only, MLP in LDS; 2: trace (and the MLP, if given, read from global memory); 3: mixed
-  // batch; 4: mixed batch with the stop (MLP in LDS)
-  const int ls = ef_q ? (stop ? 4 : 3) : !stop ? 0 : (stop->trace_max == 0 && stop->mlp ? 1 : 2);
+  // batch; 4: mixed batch with the stop (MLP in LDS); 5: w/o ME
+  const int ls = no_me ? 5 : ef_q ? (stop ? 4 : 3) : !stop ? 0 : (stop->trace_max == 0 && stop->mlp ? 1 : 2);
   if (stop) {
     a.ls_w = stop->mlp;
     a.ls_theta = stop->theta;

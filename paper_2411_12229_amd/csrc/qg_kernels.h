@@ -56,7 +56,8 @@ hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, con
 // ls_mode: 0 plain search, 1 learned stop (MLP staged in LDS, mlp_lds_bytes()
 // after the wavefront areas), 2 learned stop with trace (MLP read from global),
 // 3 per-query k and ef (k_q, ef_q set), 4 per-query k and ef with the learned
-// stop (MLP staged in LDS, as for 1)
+// stop (MLP staged in LDS, as for 1), 5 "w/o ME" (the hash holds estimated
+// vertices, not visited ones)
 hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const SearchArgs& a, int grid, int wpb,
                          size_t lds, hipStream_t st);
 int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, size_t lds);

@@ -499,6 +499,25 @@ __device__ __forceinline__ bool visited_insert(const Visited& v, uint32_t id, in
   }
 }
 
+// Per-lane insert into the set of estimated vertices (w/o ME); true if id was
+// absent, so this lane's estimate is its first.  Lanes holding the same id see
+// exactly one true.  The LDS table must keep an empty slot for every lane that
+// inserts: the caller checks the count before.
+template <bool GV>
+__device__ __forceinline__ bool seen_insert(const Visited& v, uint32_t id) {
+  if constexpr (GV) {
+    const uint32_t old = atomicOr(v.bits + (id >> 5), 1u << (id & 31));
+    return !((old >> (id & 31)) & 1u);
+  } else {
+    uint32_t s = v.slot0(id);
+    for (;;) {
+      const uint32_t old = atomicCAS(v.tab + s, kEmpty, id);
+      if (old == kEmpty) return true;
+      if (old == id) return false;
+      s = (s + 1) & v.mask;
+    }
+  }
+}
 
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
 __device__ __forceinline__ float rdlane(float v, int l) {
@@ -518,15 +537,21 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 // learned-stop modes of the search kernels
 // Kernel modes: plain search, learned stop (MLP in LDS), learned stop with
 // trace, per-query k / ef (a mixed batch), and a mixed batch with the learned
-// stop.  Each is its own instantiation, so the plain kernel carries none of the
-// others' state.
-constexpr int kLsOff = 0, kLsStop = 1, kLsTrace = 2, kMixed = 3, kMixedStop = 4;
+// stop, and the "w/o ME" ablation of Sec. 4.2.3 (a vertex enters the beam only
+// on its first estimate).  Each is its own instantiation, so the plain kernel
+// carries none of the others' state.
+constexpr int kLsOff = 0, kLsStop = 1, kLsTrace = 2, kMixed = 3, kMixedStop = 4, kNoMe = 5;
 template <int LS>
 constexpr bool has_stop = LS == kLsStop || LS == kLsTrace || LS == kMixedStop;
 template <int LS>
 constexpr bool is_mixed = LS == kMixed || LS == kMixedStop;
 template <int LS>
 constexpr bool mlp_in_lds = LS == kLsStop || LS == kMixedStop;
+// w/o ME the set holds every vertex estimated so far (the entry included)
+// rather than the visited ones: each vertex enters the beam at most once, so a
+// pop never meets a visited vertex and the set is tested only on appends
+template <int LS>
+constexpr bool no_me = LS == kNoMe;
 
 constexpr int kLsW1 = 0, kLsB1 = 64 * 16, kLsW2 = kLsB1 + 64, kLsB2 = kLsW2 + 64 * 64, kLsW3 = kLsB2 + 64,
               kLsB3 = kLsW3 + 64;
@@ -752,6 +777,10 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   beam[0] = tail;
   wave_sync();
   int size = 1, cursor = 0, nnc = 0;
+  if constexpr (no_me<LS>) {  // the entry counts as estimated: it never enters the beam again
+    visited_insert<GV>(vis, (uint32_t)a.entry, lane);
+    nvis = 1;
+  }
   float nn_wk = 0.0f;  // worst (distance, id) of NN once it holds k entries
   uint32_t nn_wi = 0;
   int expansions = 0, pops = 0, appended = 0;
@@ -789,7 +818,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       }
       bool fresh = false;
       uint32_t vend = 0;
-      if (un) fresh = !visited_probe<GV>(vis, (uint32_t)e, vend);
+      if (un) fresh = no_me<LS> || !visited_probe<GV>(vis, (uint32_t)e, vend);
       const uint64_t mf = ballot(fresh);
       const uint64_t dups = mf ? mu & ((1ull << first_lane(mf)) - 1) : mu;
       if (dups) {
@@ -821,18 +850,20 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     beam_lo[2 * c] = p | kChecked;  // every lane stores the same word
     cursor = c + 1;
     ++pops;
-    if constexpr (GV) {
-      visited_insert<GV>(vis, p, lane);
-    } else {
-      if (lane == 0) vis.tab[p_slot] = p;  // p is absent: its probe ended at this empty slot
-      wave_sync();
-    }
-    if (++nvis > vis_limit) {  // on-chip visited set full: hand the query to the overflow path
-      if (lane == 0) {
-        const int slot = atomicAdd(a.counters + 1, 1);
-        a.overflow_list[slot] = (int32_t)q;
+    if constexpr (!no_me<LS>) {
+      if constexpr (GV) {
+        visited_insert<GV>(vis, p, lane);
+      } else {
+        if (lane == 0) vis.tab[p_slot] = p;  // p is absent: its probe ended at this empty slot
+        wave_sync();
       }
-      return;
+      if (++nvis > vis_limit) {  // on-chip visited set full: hand the query to the overflow path
+        if (lane == 0) {
+          const int slot = atomicAdd(a.counters + 1, 1);
+          a.overflow_list[slot] = (int32_t)q;
+        }
+        return;
+      }
     }
     ++expansions;
 
@@ -850,7 +881,21 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const uint32_t nb = (uint32_t)b.nb;
     const uint64_t cand = pack_kv(est, nb);
     bool valid = (lane % LPN == 0) && b.nb >= 0;
-    if (valid) valid = !visited_contains<GV>(vis, nb);
+    if constexpr (no_me<LS>) {
+      if constexpr (!GV) {
+        if (nvis + (int)__popcll(ballot(valid)) > vis_limit) {  // the set could fill: overflow path
+          if (lane == 0) {
+            const int slot = atomicAdd(a.counters + 1, 1);
+            a.overflow_list[slot] = (int32_t)q;
+          }
+          return;
+        }
+      }
+      if (valid) valid = seen_insert<GV>(vis, nb);
+      nvis += (int)__popcll(ballot(valid));
+    } else {
+      if (valid) valid = !visited_contains<GV>(vis, nb);
+    }
     const int app = uni((int)__popcll(ballot(valid)));
     appended += app;
     if (size == ef) valid = valid && cand < tail;  // would fall past the cut anyway
@@ -880,7 +925,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         }
         if (!o2f_known) {
           bool fresh = false;
-          if (un) fresh = !visited_contains<GV>(vis, (uint32_t)e);
+          if (un) fresh = no_me<LS> || !visited_contains<GV>(vis, (uint32_t)e);
           const uint64_t mf = ballot(fresh);
           if (mf) {
             o2f = rdlane64(e, first_lane(mf));
@@ -1241,6 +1286,7 @@ hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const Se
     case kLsTrace: return launch_search_t<d, r, gv, kLsTrace>(a, grid, wpb, lds, st); \
     case kMixed: return launch_search_t<d, r, gv, kMixed>(a, grid, wpb, lds, st);     \
     case kMixedStop: return launch_search_t<d, r, gv, kMixedStop>(a, grid, wpb, lds, st); \
+    case kNoMe: return launch_search_t<d, r, gv, kNoMe>(a, grid, wpb, lds, st);         \
     default: return hipErrorInvalidValue;                                           \
   }
 #define QG_CASE(d, r)                  \
@@ -1262,6 +1308,7 @@ int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, siz
     case kLsTrace: return occupancy_t<d, r, gv, kLsTrace>(wpb, lds);        \
     case kMixed: return occupancy_t<d, r, gv, kMixed>(wpb, lds);            \
     case kMixedStop: return occupancy_t<d, r, gv, kMixedStop>(wpb, lds);    \
+    case kNoMe: return occupancy_t<d, r, gv, kNoMe>(wpb, lds);              \
     default: return 0;                                                    \
   }
 #define QG_CASE(d, r)                  \
