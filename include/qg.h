@@ -58,11 +58,14 @@ enum {
 /* Load an index file (4096-byte header, rotation, vertex blocks; FNV-1a-64
  * checksum verified) into device memory of `device`.  *out receives a new
  * index, NULL on error.  Supported (D, R): D in {96, 128, 768, 960} (or any
- * multiple of 32 up to 1024 for which the library was built), R in {32, 64}. */
+ * multiple of 32 up to 1024 for which the library was built), R in {32, 64}.
+ * QG_EFORMAT also for a neighbour id outside [-1, N) or one that a vertex's
+ * list holds twice. */
 int qg_load_index(const char *path, int device, qg_index **out);
 
 /* Build an index on `device` from vectors[n][d] (fp32), graph[n][r] (int32
- * ids in [0, n), -1 = empty slot), rotation[d][d] (fp32, the matrix M =
+ * ids in [0, n), -1 = empty slot; no id twice in one list, as Algorithm 2's
+ * lists of distinct neighbours: QG_EINVAL otherwise), rotation[d][d] (fp32, the matrix M =
  * P^{-1} applied to vectors, Eq. rotation) and the entry vertex.  All three
  * arrays are device pointers; they are read during the call and may be freed
  * afterwards.  Encodes every block on the GPU (Sec. 3.1.1 normalisation by

@@ -229,6 +229,22 @@ int qg_index_info(const qg_index* idx, int64_t* n, int32_t* d, int32_t* r, int32
   return QG_OK;
 }
 
+// True if some vertex lists one neighbour id twice (-1 padding aside).  The
+// search merges a vertex's new candidates by rank, and two equal candidate
+// words would share a rank; a graph of distinct neighbours (as Algorithm 2
+// builds) never has them, so such input is refused.
+static bool has_repeated_id(const int32_t* g, int64_t n, int r) {
+  std::vector<int32_t> stamp((size_t)n, -1);  // stamp[v] = the last list that held v
+  for (int64_t u = 0; u < n; ++u)
+    for (int j = 0; j < r; ++j) {
+      const int32_t v = g[u * r + j];
+      if (v < 0) continue;
+      if (stamp[(size_t)v] == (int32_t)u) return true;
+      stamp[(size_t)v] = (int32_t)u;
+    }
+  return false;
+}
+
 int qg_build_index(const float* vectors, int64_t n, int32_t d, const int32_t* graph, int32_t r,
                    const float* rotation, int32_t entry, int device, qg_index** out) {
   if (!out) return fail(QG_EINVAL, "out is NULL");
@@ -251,6 +267,13 @@ int qg_build_index(const float* vectors, int64_t n, int32_t d, const int32_t* gr
     HIP_TRY(hipMemcpy(h.data(), graph, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost), "copy graph");
     for (int32_t v : h)
       if (v < -1 || v >= n) return fail(QG_EINVAL, "graph id out of range");
+    bool rep = false;
+    try {
+      rep = has_repeated_id(h.data(), n, r);
+    } catch (...) {
+      return fail(QG_ENOMEM, "host buffer");
+    }
+    if (rep) return fail(QG_EINVAL, "a neighbour list repeats an id");
   }
   qg_index* idx = new qg_index;
   idx->device = device;
@@ -348,6 +371,16 @@ int qg_load_index(const char* path, int device, qg_index** out) {
         if (x < -1 || x >= N) return fail(QG_EFORMAT, "neighbour id out of range");
       }
     }
+    bool rep = false;
+    try {
+      std::vector<int32_t> ids((size_t)(N * R));
+      for (int64_t v = 0; v < N; ++v)
+        std::memcpy(ids.data() + v * R, blk0 + v * B + qgl::off_nbr(D, R), sizeof(int32_t) * (size_t)R);
+      rep = has_repeated_id(ids.data(), N, R);
+    } catch (...) {
+      return fail(QG_ENOMEM, "host buffer");
+    }
+    if (rep) return fail(QG_EFORMAT, "a neighbour list repeats an id");
   }
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");

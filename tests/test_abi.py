@@ -50,3 +50,30 @@ def test_error_paths_without_device():
     assert lib.qg_server_submit(None, None, 1, 1, ctypes.c_uint64(0)) == -1
     lib.qg_server_destroy(None)
     lib.qg_free_index(None)
+
+
+def test_load_refuses_repeated_neighbour_ids(tmp_path):
+    """An index file whose neighbour list holds an id twice is refused before
+    any device work (the search's merge needs distinct neighbours)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    X, _ = synth.gen_data(1, n=300, nq=1)
+    M = synth.rotation(128, 3)
+    G = synth.knn_graph(X, 32, 4)
+    e = synth.medoid(X)
+    lib = ctypes.CDLL(LIB)
+    lib.qg_last_error.restype = ctypes.c_char_p
+    out = ctypes.c_void_p(1)
+    G[17, 9] = G[17, 3]
+    path = str(tmp_path / "rep.qgi")
+    oracle.write_index(path, oracle.encode(X, G, M), 128, 32, e, M)
+    assert lib.qg_load_index(path.encode(), 0, ctypes.byref(out)) == -4 and out.value is None
+    assert b"repeats" in lib.qg_last_error()
+    # -1 padding may repeat
+    G = synth.knn_graph(X, 32, 4)
+    G[17, 9] = G[17, 3] = -1
+    oracle.write_index(path, oracle.encode(X, G, M), 128, 32, e, M)
+    lib.qg_load_index(path.encode(), 0, ctypes.byref(out))
+    assert b"repeats" not in (lib.qg_last_error() or b"")

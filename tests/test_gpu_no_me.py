@@ -107,3 +107,39 @@ def test_no_me_only_plain_search(cfg1):
     with pytest.raises(qg.QGError) as ex:
         c["idx"].search_stop(Qd, 10, 10, None, trace_max=2, flags=qg.QG_SEARCH_NO_ME)
     assert ex.value.code == qg.QG_EUNSUPPORTED
+
+
+def test_self_edges_and_empty_slots():
+    """A graph whose lists point at their own vertex and hold -1 slots: both
+    searches (with and without multiple estimates) equal the oracle's.  A list
+    that repeats an id is refused at build time, before any kernel runs."""
+    X, Q = synth.gen_data(1, n=2000, nq=60)
+    M = synth.rotation(128, 23)
+    G = synth.knn_graph(X, 32, 24, n_long=4)
+    rng = np.random.default_rng(25)
+    n = len(X)
+    G[rng.choice(n, 200, replace=False), 5] = -1
+    sl = rng.choice(n, 200, replace=False)
+    G[sl, 7] = sl  # self edges
+    for row in G:  # the self edges above must not repeat an id of their list
+        r = row[row >= 0]
+        assert len(np.unique(r)) == len(r)
+    e = synth.medoid(X)
+    say("self edges and empty slots: N=2000 D=128 R=32")
+    idx = qg.qg_build_index(T(X), T(G), T(M), e)
+    blocks = oracle.encode(X, G, M)
+    assert np.array_equal(idx.blocks().cpu().numpy(), blocks)
+    for flags, oflags in ((0, 0), (qg.QG_SEARCH_NO_ME, oracle.NO_ME)):
+        for k, ef in ((10, 40), (32, 200)):
+            ids, dists, st = idx.search(T(Q), k, ef, flags=flags, stats=True)
+            torch.cuda.synchronize()
+            oi, od, os_ = oracle.search(blocks, 128, 32, e, M, Q, k, ef, flags=oflags, with_stats=True)
+            ctx = f"flags={flags} k={k} ef={ef}"
+            assert np.array_equal(ids.cpu().numpy(), oi), ctx
+            assert np.array_equal(dists.cpu().numpy(), od), ctx
+            assert np.array_equal(st.cpu().numpy()[:, :3], os_[:, :3]), ctx
+    G2 = G.copy()
+    G2[11, 9] = G2[11, 3] if G2[11, 3] >= 0 else G2[11, 4]
+    with pytest.raises(qg.QGError) as ex:
+        qg.qg_build_index(T(X), T(G2), T(M), e)
+    assert ex.value.code == qg.QG_EINVAL
