@@ -55,7 +55,7 @@ def oracle_blocks_for(X, G, M, verts):
     return blocks
 
 
-def check_full_size(cfg, X, Q, G, M, k, ef, launch, n_blocks=256, n_queries=48, seed=0):
+def check_full_size(cfg, X, Q, G, M, k, ef, launch, n_blocks=256, n_queries=48, seed=0, no_me_ef=0):
     N, D = X.shape
     R = G.shape[1]
     e = synth.medoid(X)
@@ -77,17 +77,28 @@ def check_full_size(cfg, X, Q, G, M, k, ef, launch, n_blocks=256, n_queries=48, 
     assert np.array_equal(dists[qs], od), "distances differ"
     assert np.array_equal(st[qs, :3], os_[:, :3]), "counters differ"
     say(f"  {n_queries} sampled queries equal; mean expansions {st[:, 0].mean():.1f}")
+    if no_me_ef:  # the w/o ME ablation on the same index and sample
+        ids, dists, st = idx.search(T(Q), k, no_me_ef, flags=qg.QG_SEARCH_NO_ME, stats=True)
+        torch.cuda.synchronize()
+        ids, dists, st = ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
+        oi, od, os_ = oracle.search(dev_blocks, D, R, e, M, Q[qs], k, no_me_ef, flags=oracle.NO_ME, with_stats=True)
+        bad = np.nonzero((ids[qs] != oi).any(axis=1))[0]
+        assert bad.size == 0, f"w/o ME: ids differ for queries {qs[bad][:10].tolist()}"
+        assert np.array_equal(dists[qs], od), "w/o ME: distances differ"
+        assert np.array_equal(st[qs, :3], os_[:, :3]), "w/o ME: counters differ"
+        say(f"  w/o ME ef={no_me_ef}: {n_queries} sampled queries equal")
 
 
 def test_sift_shaped_full_size():
     """1M x 128, R = 32, the benchmark's input graph, 10,000 queries at the
-    benchmark's beam (72) and tuned launch shape, and at the default shape."""
+    benchmark's beam (72) and tuned launch shape, and at the default shape;
+    the w/o ME search at the beam that reaches the same recall (48)."""
     c = synth.SIFT_LIKE
     X, Q = synth.gen_data(c)
     M = synth.rotation(128, synth.seed(c, "rotation"))
     G = synth.knn_graph(X, 32, synth.seed(c, "long"), device=DEV)
     check_full_size(c, X, Q, G, M, 10, 72, (8, 4, 24))
-    check_full_size(c, X, Q, G, M, 10, 72, (4, 3, 0), seed=1)
+    check_full_size(c, X, Q, G, M, 10, 72, (4, 3, 0), seed=1, no_me_ef=48)
 
 
 def test_serving_shaped_full_size():
