@@ -165,9 +165,10 @@ def main():
             if len(sweep) >= 2 and ef >= 64:
                 break
     # the coarse grid brackets the target recall between two beam sizes; the
-    # smallest one that reaches it is found between them in steps of 8
+    # smallest one that reaches it is found between them in steps of 4 (the
+    # beam's storage granule)
     if chosen is not None and not args.ef and len(sweep) >= 2 and sweep[-2]["recall@10"] < args.target:
-        for ef in range(sweep[-2]["ef"] + 8, chosen[0], 8):
+        for ef in range(sweep[-2]["ef"] + 4, chosen[0], 4):
             rec, s = measure(ef)
             if rec >= args.target:
                 chosen = (ef, rec, s)
