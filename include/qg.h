@@ -87,8 +87,9 @@ int qg_search(const qg_index *idx, const float *queries, int64_t nq, int32_t k, 
 /* qg_search with flags (QG_SEARCH_*) and optional per-query counters
  * out_stats[nq][4] (int32, device, nullable): expansions (vertices whose
  * exact distance was computed), pops from the beam, appended candidates, and
- * 1 if the query was finished by the overflow path (its visited set outgrew
- * on-chip memory; results are identical either way). */
+ * 1 if the query was finished by the overflow path (its visited set, or
+ * without ME its set of estimated vertices, outgrew on-chip memory; results
+ * are identical either way). */
 int qg_search_ex(const qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                  int32_t *out_ids, float *out_dists, int32_t *out_stats);
 
