@@ -608,7 +608,7 @@ def ls_study(args, dev):
             rows.append({"target": target, "fixed": None, "learned_stop": None})
             continue
         if lo is not None:
-            for ef in range(lo + 8, hi, 8):
+            for ef in range(lo + 4, hi, 4):  # the same refinement as the bench line's
                 if fixed(ef)["recall@10"] >= target:
                     hi = ef
                     break
