@@ -233,17 +233,21 @@ int qg_index_info(const qg_index* idx, int64_t* n, int32_t* d, int32_t* r, int32
 // search merges a vertex's new candidates by rank, and two equal candidate
 // words would share a rank; a graph of distinct neighbours (as Algorithm 2
 // builds) never has them, so such input is refused.
-static bool has_repeated_id(const int32_t* g, int64_t n, int r) {
+// id_at(u, j) gives neighbour j of vertex u.
+extern "C++" {
+template <class IdAt>
+static bool has_repeated_id(int64_t n, int r, IdAt id_at) {
   std::vector<int32_t> stamp((size_t)n, -1);  // stamp[v] = the last list that held v
   for (int64_t u = 0; u < n; ++u)
     for (int j = 0; j < r; ++j) {
-      const int32_t v = g[u * r + j];
+      const int32_t v = id_at(u, j);
       if (v < 0) continue;
       if (stamp[(size_t)v] == (int32_t)u) return true;
       stamp[(size_t)v] = (int32_t)u;
     }
   return false;
 }
+}  // extern "C++"
 
 int qg_build_index(const float* vectors, int64_t n, int32_t d, const int32_t* graph, int32_t r,
                    const float* rotation, int32_t entry, int device, qg_index** out) {
@@ -269,7 +273,7 @@ int qg_build_index(const float* vectors, int64_t n, int32_t d, const int32_t* gr
       if (v < -1 || v >= n) return fail(QG_EINVAL, "graph id out of range");
     bool rep = false;
     try {
-      rep = has_repeated_id(h.data(), n, r);
+      rep = has_repeated_id(n, r, [&](int64_t u, int j) { return h[(size_t)(u * r + j)]; });
     } catch (...) {
       return fail(QG_ENOMEM, "host buffer");
     }
@@ -373,10 +377,12 @@ int qg_load_index(const char* path, int device, qg_index** out) {
     }
     bool rep = false;
     try {
-      std::vector<int32_t> ids((size_t)(N * R));
-      for (int64_t v = 0; v < N; ++v)
-        std::memcpy(ids.data() + v * R, blk0 + v * B + qgl::off_nbr(D, R), sizeof(int32_t) * (size_t)R);
-      rep = has_repeated_id(ids.data(), N, R);
+      const int64_t off = qgl::off_nbr(D, R);
+      rep = has_repeated_id(N, R, [&](int64_t u, int j) {
+        int32_t x;
+        std::memcpy(&x, blk0 + u * B + off + 4 * j, 4);
+        return x;
+      });
     } catch (...) {
       return fail(QG_ENOMEM, "host buffer");
     }
