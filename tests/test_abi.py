@@ -77,3 +77,19 @@ def test_load_refuses_repeated_neighbour_ids(tmp_path):
     oracle.write_index(path, oracle.encode(X, G, M), 128, 32, e, M)
     lib.qg_load_index(path.encode(), 0, ctypes.byref(out))
     assert b"repeats" not in (lib.qg_last_error() or b"")
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The Python binding has no fallback: a copy of it next to no built
+    library refuses to import."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_2411_12229_amd"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text("")
+    shutil.copy(os.path.join(ROOT, "paper_2411_12229_amd", "qg.py"), pkg / "qg.py")
+    r = subprocess.run([sys.executable, "-c", "from paper_2411_12229_amd import qg"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "libqg.so is missing" in r.stderr
