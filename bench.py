@@ -67,6 +67,9 @@ def main():
                     help="wpb,hash_factor,cu_waves: set this launch shape for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--no-ablation", action="store_true", help="skip the w/o ME leg")
+    ap.add_argument("--ablation-ef", default="",
+                    help="comma-separated beam sizes of the w/o ME leg (default: 16,32,48,64,96,128,192 and the "
+                         "bench's own)")
     ap.add_argument("--ls-study", action="store_true",
                     help="instead of the benchmark line: learned stop against fixed ef at recall@10 0.90 / 0.95 / "
                          "0.99 (one JSON line)")
@@ -230,13 +233,15 @@ def main():
     # the "w/o ME" ablation (Sec. 4.2.3): a vertex enters the beam only on its
     # first estimate; recall and rate against the beam size, beside the sweep
     no_me = None
-    if not args.no_ablation and gt is not None:
+    if not args.no_ablation:
         no_me = []
-        for ef_a in sorted({16, 32, 48, 64, ef, 96, 128, 192}):
+        ablation_efs = ({int(x) for x in args.ablation_ef.split(",")} if args.ablation_ef
+                        else {16, 32, 48, 64, ef, 96, 128, 192})
+        for ef_a in sorted(ablation_efs):
             with torch.cuda.stream(stream):
                 ids_a, _, st_a = idx.search(Qs, k, ef_a, flags=qg.QG_SEARCH_NO_ME, stats=True)
             stream.synchronize()
-            rec_a = synth.recall(ids_a.cpu().numpy(), gt, k)
+            rec_a = synth.recall(ids_a.cpu().numpy(), gt, k) if gt is not None else float("nan")
             sa = st_a.cpu().numpy()
             t1 = time.time()
             with torch.cuda.stream(stream):
@@ -244,7 +249,7 @@ def main():
                     idx.search(Qs, k, ef_a, flags=qg.QG_SEARCH_NO_ME)
             stream.synchronize()
             qps_a = 3 * args.nq / (time.time() - t1)
-            no_me.append({"ef": ef_a, "recall@10": round(rec_a, 4), "qps_host_clock": round(qps_a),
+            no_me.append({"ef": ef_a, "recall@10": round(rec_a, 4) if gt is not None else None, "qps_host_clock": round(qps_a),
                           "mean_expansions": round(float(sa[:, 0].mean()), 2),
                           "mean_appended": round(float(sa[:, 2].mean()), 2),
                           "overflow_queries": int(sa[:, 3].sum())})
