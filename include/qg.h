@@ -55,8 +55,11 @@ enum {
 #define QG_MAX_EF 2048
 #define QG_MAX_K 1024
 
-/* Load an index file (4096-byte header, rotation, vertex blocks; FNV-1a-64
- * checksum verified) into device memory of `device`.  *out receives a new
+/* Load an index file into device memory of `device`: a 4096-byte header,
+ * the rotation M, then one contiguous block per vertex laid out as the
+ * paper's data layout prescribes (Sec. 3.1.3: raw vector, then the FastScan
+ * data of its neighbours -- codes and two factors each -- then the neighbour
+ * ids, padded to 128 bytes), FNV-1a-64 checksum verified.  *out receives a new
  * index, NULL on error.  Supported (D, R): D in {96, 128, 768, 960} (or any
  * multiple of 32 up to 1024 for which the library was built), R in {32, 64}.
  * QG_EFORMAT also for a neighbour id outside [-1, N) or one that a vertex's
@@ -69,7 +72,7 @@ int qg_load_index(const char *path, int device, qg_index **out);
  * P^{-1} applied to vectors, Eq. rotation) and the entry vertex.  All three
  * arrays are device pointers; they are read during the call and may be freed
  * afterwards.  Encodes every block on the GPU (Sec. 3.1.1 normalisation by
- * the holding vertex; Alg. 2 "prepare data for FastScan"). Synchronous. */
+ * the holding vertex; the FastScan data of every vertex built in Alg. 2). Synchronous. */
 int qg_build_index(const float *vectors, int64_t n, int32_t d, const int32_t *graph, int32_t r,
                    const float *rotation, int32_t entry, int device, qg_index **out);
 
@@ -163,6 +166,8 @@ int qg_estimate(const qg_index *idx, const float *queries, const int32_t *vertex
 int qg_copy_blocks(const qg_index *idx, int64_t first, int64_t count, void *dst);
 
 /* Select the HIP stream (hipStream_t) for later work; NULL = null stream.
+ * (Runtime plumbing: the paper's search is single-threaded on a CPU and has
+ * no counterpart.)
  * Every search call only enqueues kernels on this stream (no host
  * synchronisation, no memset), so a caller may record searches into a HIP
  * graph by capturing this stream.  Calls on one index share its scratch and
@@ -259,7 +264,10 @@ void qg_server_destroy(qg_server *s);
  * replay only while no later call has grown it.  Synchronous. */
 int qg_reserve(qg_index *idx, int64_t nq);
 
-/* Index geometry; any output pointer may be NULL. Host pointers. */
+/* Index geometry: vector count n, dimension d, out-degree r (R of Sec. 3.2),
+ * the entry vertex e of Algorithm 1, and the byte size of one vertex block
+ * (Sec. 3.1.3 layout, padded to 128 bytes).  Any output pointer may be NULL.
+ * Host pointers. */
 int qg_index_info(const qg_index *idx, int64_t *n, int32_t *d, int32_t *r, int32_t *entry, int64_t *block_bytes);
 
 /* Kernel timing with HIP events recorded on the index's stream around every

@@ -125,8 +125,8 @@ static void encode_edge(const float *xo, const float *xc_raw, const float *ro, c
 }
 
 /* Build every vertex block from the vectors X[N][D], the graph G[N][R]
- * (-1 = empty slot) and the rotation M (Sec. 3.1.3 data layout; Alg. 2
- * "prepare data for FastScan"). */
+ * (-1 = empty slot) and the rotation M (Sec. 3.1.3 data layout; the
+ * FastScan data of every vertex that Alg. 2 builds after its last round). */
 int qgo_encode(const float *X, int64_t N, int D, const int32_t *G, int R, const float *M, uint8_t *blocks,
                int nthreads) {
   if (D <= 0 || D % 8 || R <= 0 || N <= 0) return -1;

@@ -83,6 +83,7 @@ struct qg_index {
   int wpb_pref = 4;
   int hash_factor = 3;
   int cu_waves = 0;  // cap on resident wavefronts per compute unit (0 = as many as fit)
+  int cus = 256;     // compute units of the device (read at creation; sizes the persistent grid)
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev[2];  // pairs per kernel class
@@ -98,6 +99,9 @@ static int validate_shape(int64_t n, int d, int r) {
 }
 
 static int alloc_common(qg_index* idx) {
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, idx->device), "compute unit count");
+  idx->cus = cus > 0 ? cus : 1;
   HIP_TRY(hipMalloc(&idx->rot, sizeof(float) * idx->D * idx->D), "hipMalloc rotation");
   HIP_TRY(hipMalloc(&idx->blocks, (size_t)(idx->N * idx->block_bytes)), "hipMalloc blocks");
   HIP_TRY(hipMalloc(&idx->counters, sizeof(int) * kCounters), "hipMalloc counters");
@@ -191,6 +195,7 @@ qg_index* make_view(const qg_index* base) {
   v->wpb_pref = base->wpb_pref;
   v->hash_factor = base->hash_factor;
   v->cu_waves = base->cu_waves;
+  v->cus = base->cus;
   v->fb_slots = base->fb_slots;
   v->fb_words = base->fb_words;
   if (hipMalloc(&v->counters, sizeof(int) * kCounters) != hipSuccess ||
@@ -555,7 +560,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   if (occ <= 0) occ = 1;
   if (idx->cu_waves > 0) occ = std::min(occ, std::max(1, idx->cu_waves / wpb));
   int64_t want = (nq + wpb - 1) / wpb;
-  int grid = (int)std::min<int64_t>(want, (int64_t)occ * 256);
+  int grid = (int)std::min<int64_t>(want, (int64_t)occ * idx->cus);
 
   if ((rc = record(idx, 0, true))) return rc;
   HIP_TRY(qgk::launch_rotate(queries, nq, idx->D, idx->rot, idx->qrot, idx->counters, kCounters, idx->stream),

@@ -406,7 +406,10 @@ class Server:
         h = ctypes.c_void_p()
         _check(_lib.qg_server_create(index.handle, streams, max_batch, k_max, ef_max, ctypes.byref(h)))
         self._h, self._index, self.d, self.k_max = h, index, index.d, k_max
-        self._replay = None
+        # host arrays of accepted traces: the library's threads read them (the
+        # producer, and dispatch through each pending request's row pointer)
+        # until a drain succeeds or the server is destroyed
+        self._traces = []
         self._stop = None
 
     def set_stop(self, mlp: torch.Tensor | None, theta: float = 0.0, t_min: int = 8, t_every: int = 4) -> None:
@@ -446,15 +449,16 @@ class Server:
         n = arrs[0].shape[0]
         if arrs[0].shape != (n, self.d) or arrs[1].shape != (n,) or arrs[2].shape != (n,) or arrs[3].shape != (n,):
             raise ValueError("trace shape mismatch")
-        self._replay = arrs  # kept alive until drain
         _check(_lib.qg_server_replay(self._h, _host(arrs[0], np.float32, "queries"), _host(arrs[1], np.int32, "k"),
                                      _host(arrs[2], np.int32, "ef"), _host(arrs[3], np.float64, "arrival_s"), n))
+        self._traces.append(arrs)  # accepted: kept alive until a drain succeeds or close()
 
     def drain(self, timeout_s: float = 120.0) -> None:
-        try:
-            _check(_lib.qg_server_drain(self._h, float(timeout_s)))
-        finally:
-            self._replay = None
+        """Wait until every submitted request has finished.  On a time-out or
+        error the traces stay referenced (pending requests still point into
+        them) until close()."""
+        _check(_lib.qg_server_drain(self._h, float(timeout_s)))
+        self._traces = []
 
     def stats(self):
         v = [ctypes.c_int64() for _ in range(4)]
@@ -463,9 +467,9 @@ class Server:
 
     def close(self) -> None:
         if self._h:
-            _lib.qg_server_destroy(self._h)
+            _lib.qg_server_destroy(self._h)  # joins the library's threads
             self._h = None
-            self._replay = None
+            self._traces = []
 
     def __del__(self):
         try:

@@ -163,3 +163,38 @@ def test_server_argument_errors(cfg1):
         assert tags.tolist() == [7] and (ids[0, 5:] == -1).all()
     finally:
         srv.close()
+
+
+def test_trace_outlives_a_timed_out_drain(cfg1):
+    """A trace the binding had to convert (float64 queries, int64 k and ef) is
+    held by the binding itself.  A drain that times out must keep it alive:
+    pending requests still point into its rows, and a second replay refused
+    while the first runs must not drop it either.  After a full drain every
+    result equals that query searched alone."""
+    import gc
+    c = cfg1
+    rng = np.random.default_rng(31)
+    n = 3000
+    sel = rng.integers(0, len(c["Q"]), n)
+    Q64 = c["Q"][sel].astype(np.float64)  # converted (copied) by the binding
+    ks = np.full(n, 10, np.int64)
+    efs = np.full(n, 256, np.int64)
+    arrival = np.linspace(0.0, 0.02, n)
+    srv = qg.Server(c["idx"], streams=2, max_batch=256, k_max=10, ef_max=256)
+    try:
+        srv.replay(Q64, ks, efs, arrival)
+        with pytest.raises(qg.QGError):  # a second replay while the first runs is refused
+            srv.replay(Q64[:2], ks[:2], efs[:2], arrival[:2])
+        try:
+            srv.drain(timeout_s=1e-6)  # the producer finishes first; the searches may still run
+        except qg.QGError:
+            pass
+        del Q64
+        gc.collect()
+        srv.drain()
+        tags, ids, dists, _ = _collect(srv, n)
+    finally:
+        srv.close()
+    assert sorted(tags.tolist()) == list(range(n))
+    gi, gd = c["idx"].search(T(c["Q"][sel[tags]]), 10, 256)
+    assert np.array_equal(ids, gi.cpu().numpy()) and np.array_equal(dists, gd.cpu().numpy())
