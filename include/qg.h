@@ -264,6 +264,25 @@ void qg_server_destroy(qg_server *s);
  * replay only while no later call has grown it.  Synchronous. */
 int qg_reserve(qg_index *idx, int64_t nq);
 
+/* For callers that cannot allocate device memory during a search (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): qg_search_ex with the same arguments, results and errors, but
+ * its per-call scratch (queue counters, rotated queries, overflow list) lives
+ * in a fixed device array of QG_NOALLOC_SCRATCH_BYTES compiled into the
+ * library, one copy per device held until the process ends, instead of the
+ * index's scratch that grows on demand.  The call allocates and frees
+ * nothing.  nq may be at most (QG_NOALLOC_SCRATCH_BYTES - 256) / (4 d + 4)
+ * (32,513 queries at d = 128, 4,364 at d = 960); a larger batch gives
+ * QG_EUNSUPPORTED before anything is enqueued.  Every call on a device, for
+ * any index and on any stream, shares that device's array, which keeps the
+ * last call's contents (the call's first kernel clears the counters): calls
+ * that overlap in time on one device race and give wrong results.  The
+ * overflow pass uses the bitsets the index allocated when it was created.
+ * Not recorded by qg_timing. */
+#define QG_NOALLOC_SCRATCH_BYTES (16 << 20)
+int qg_search_noalloc(const qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                      int32_t *out_ids, float *out_dists, int32_t *out_stats);
+
 /* Index geometry: vector count n, dimension d, out-degree r (R of Sec. 3.2),
  * the entry vertex e of Algorithm 1, and the byte size of one vertex block
  * (Sec. 3.1.3 layout, padded to 128 bytes).  Any output pointer may be NULL.

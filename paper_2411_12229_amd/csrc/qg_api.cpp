@@ -470,11 +470,21 @@ int qg_rotate(const qg_index* idx, const float* in, int64_t n, float* out) {
   return QG_OK;
 }
 
+// Per-call scratch taken from the fixed device array instead of the index
+// (the allocation-free entry point).
+struct FixedScratch {
+  float* qrot;
+  int32_t* overflow;
+  int* counters;
+};
+
 // Every search entry point ends here.  k and ef are the values of a uniform
 // batch, or the bounds of a mixed one (k_q, ef_q: per-query device arrays).
+// With fx, nothing is allocated: the rotated queries, overflow list and queue
+// counters live in *fx, and no timing events are recorded.
 static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, int32_t k, int32_t ef,
                        const int32_t* k_q, const int32_t* ef_q, int32_t flags, const qg_stop_params* stop,
-                       int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+                       int32_t* out_ids, float* out_dists, int32_t* out_stats, const FixedScratch* fx = nullptr) {
   qg_index* idx = const_cast<qg_index*>(cidx);
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (nq < 0) return fail(QG_EINVAL, "nq < 0");
@@ -493,8 +503,10 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   if (nq > 0x7fffffffLL) return fail(QG_EINVAL, "nq too large");
   if (!queries || !out_ids || !out_dists) return fail(QG_EINVAL, "NULL array");
   DeviceGuard g(idx->device);
-  int rc = ensure_scratch(idx, nq);
+  int rc = fx ? QG_OK : ensure_scratch(idx, nq);
   if (rc) return rc;
+  float* const qrot = fx ? fx->qrot : idx->qrot;
+  int* const counters = fx ? fx->counters : idx->counters;
 
   const int ef_cap = (ef + 3) / 4 * 4;
   const int k_cap = (k + 3) / 4 * 4;
@@ -513,7 +525,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   a.block_bytes = idx->block_bytes;
   a.N = idx->N;
   a.queries = queries;
-  a.qrot = idx->qrot;
+  a.qrot = qrot;
   a.nq = nq;
   a.k = k;
   a.ef = ef;
@@ -528,8 +540,8 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   a.out_ids = out_ids;
   a.out_dists = out_dists;
   a.out_stats = out_stats;
-  a.counters = idx->counters;
-  a.overflow_list = idx->overflow;
+  a.counters = counters;
+  a.overflow_list = fx ? fx->overflow : idx->overflow;
   a.fb_bits = idx->fb_bits;
   a.fb_words = idx->fb_words;
   // ls_mode 1: stop only, MLP in LDS; 2: trace (and the MLP, if given, read from global memory); 3: mixed
@@ -562,13 +574,15 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   int64_t want = (nq + wpb - 1) / wpb;
   int grid = (int)std::min<int64_t>(want, (int64_t)occ * idx->cus);
 
-  if ((rc = record(idx, 0, true))) return rc;
-  HIP_TRY(qgk::launch_rotate(queries, nq, idx->D, idx->rot, idx->qrot, idx->counters, kCounters, idx->stream),
+  // the rotation's first workgroup also clears the queue counters (a kernel,
+  // not a memset, so the call can be captured into a graph)
+  if (!fx && (rc = record(idx, 0, true))) return rc;
+  HIP_TRY(qgk::launch_rotate(queries, nq, idx->D, idx->rot, qrot, counters, kCounters, idx->stream),
           "rotate queries");
-  if ((rc = record(idx, 0, false))) return rc;
-  if ((rc = record(idx, 1, true))) return rc;
+  if (!fx && (rc = record(idx, 0, false))) return rc;
+  if (!fx && (rc = record(idx, 1, true))) return rc;
   HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, a, grid, wpb, lds, idx->stream), "search");
-  if ((rc = record(idx, 1, false))) return rc;
+  if (!fx && (rc = record(idx, 1, false))) return rc;
   // overflow pass: one wavefront per workgroup, one bitset each
   HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, a, idx->fb_slots, 1, (size_t)Lf.total + extra, idx->stream),
           "search overflow pass");
@@ -705,6 +719,30 @@ int qg_reserve(qg_index* idx, int64_t nq) {
 int qg_search_ex(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                  int32_t* out_ids, float* out_dists, int32_t* out_stats) {
   return qg_search_stop(idx, queries, nq, k, ef, flags, nullptr, out_ids, out_dists, out_stats);
+}
+
+int qg_search_noalloc(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                      int32_t* out_ids, float* out_dists, int32_t* out_stats) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (nq < 0) return fail(QG_EINVAL, "nq < 0");
+  static_assert(QG_NOALLOC_SCRATCH_BYTES == qgk::kNoAllocScratchBytes, "scratch size in qg.h");
+  // layout: counters in [0, 256), then nq x d rotated queries, then nq overflow slots
+  const int64_t max_nq = (QG_NOALLOC_SCRATCH_BYTES - 256) / (4LL * idx->D + 4);
+  if (nq > max_nq)
+    return fail(QG_EUNSUPPORTED, "nq = " + std::to_string(nq) + " exceeds the allocation-free limit of " +
+                                     std::to_string(max_nq) + " queries at d = " + std::to_string(idx->D));
+  if (nq == 0) return search_impl(idx, queries, nq, k, ef, nullptr, nullptr, flags, nullptr, out_ids, out_dists,
+                                  out_stats);  // argument checks only
+  uint8_t* base = nullptr;
+  {
+    DeviceGuard g(idx->device);
+    HIP_TRY(qgk::noalloc_scratch(idx->device, &base), "fixed scratch address");
+  }
+  FixedScratch fx;
+  fx.counters = reinterpret_cast<int*>(base);
+  fx.qrot = reinterpret_cast<float*>(base + 256);
+  fx.overflow = reinterpret_cast<int32_t*>(base + 256 + 4 * nq * idx->D);
+  return search_impl(idx, queries, nq, k, ef, nullptr, nullptr, flags, nullptr, out_ids, out_dists, out_stats, &fx);
 }
 
 int qg_search(const qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t* out_ids,

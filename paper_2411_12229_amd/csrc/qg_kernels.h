@@ -48,6 +48,13 @@ struct EstimateArgs {
   float* out_dist;
 };
 
+// Allocation-free search: size of the fixed per-device scratch array and its
+// device address on `device` (which must be current); the address is looked
+// up once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, uint8_t** out);
+
 bool shape_supported(int D, int R);
 hipError_t launch_rotate(const float* in, int64_t n, int D, const float* M, float* out, int* zero, int nzero,
                          hipStream_t st);

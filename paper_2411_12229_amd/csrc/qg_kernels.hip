@@ -11,10 +11,34 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "qg_kernels.h"
 #include "qg_layout.h"
 
 namespace qgk {
+
+// Fixed device scratch of the allocation-free search entry point (queue
+// counters, rotated queries, overflow list), one copy per device for as long
+// as the library is loaded.  Host code must not pass `scratch` itself to a
+// kernel (in host code it names a host-side stand-in); it takes the device
+// address from noalloc_scratch().
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, uint8_t** out) {
+  static std::mutex mu;
+  static uint8_t* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {  // once per device, with that device current
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<uint8_t*>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 

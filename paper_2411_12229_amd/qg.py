@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libqg.so")
 QG_OK, QG_EINVAL, QG_ENOMEM, QG_EIO, QG_EFORMAT, QG_EDEVICE, QG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 QG_SEARCH_NO_ME = 1
 QG_SEARCH_SMALL_HASH = 2
+QG_NOALLOC_SCRATCH_BYTES = 16 << 20
 QG_MAX_EF = 2048
 QG_MAX_K = 1024
 QG_STOP_MLP_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
@@ -53,6 +54,7 @@ def _load():
         "qg_save_index": ([P, ctypes.c_char_p], c_int),
         "qg_search": ([P, P, i64, i32, i32, P, P], c_int),
         "qg_search_ex": ([P, P, i64, i32, i32, i32, P, P, P], c_int),
+        "qg_search_noalloc": ([P, P, i64, i32, i32, i32, P, P, P], c_int),
         "qg_search_stop": ([P, P, i64, i32, i32, i32, ctypes.POINTER(StopParams), P, P, P], c_int),
         "qg_search_mixed": ([P, P, i64, P, P, i32, i32, i32, P, P, P], c_int),
         "qg_search_mixed_stop": ([P, P, i64, P, P, i32, i32, i32, ctypes.POINTER(StopParams), P, P, P], c_int),
