@@ -64,7 +64,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shape instead of the one qg_autotune picks for the benchmark queries")
     ap.add_argument("--launch", default="",
-                    help="wpb,hash_factor,cu_waves: set this launch shape for every search instead of autotuning")
+                    help="wpb,hash_factor,cu_waves[,beam]: set this launch shape (beam 1: in registers where the "
+                         "beam size allows, the default; 0: in LDS) for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--no-ablation", action="store_true", help="skip the w/o ME leg")
     ap.add_argument("--ablation-ef", default="",
@@ -132,9 +133,10 @@ def main():
         Qs = Qd.clone()
     stream.synchronize()
 
-    shape = (4, 3, 0)  # the library's default launch shape
+    shape = (4, 3, 0, 1)  # the library's default launch shape
     if args.launch:
         shape = tuple(int(x) for x in args.launch.split(","))
+        shape = shape + (1,) * (4 - len(shape))
         idx.set_launch(*shape)
 
     def run(ef, stats=False):
@@ -211,13 +213,13 @@ def main():
             idx.search(Qs, k, ef)
 
     tuned = {"waves_per_workgroup": shape[0], "hash_factor": shape[1], "resident_waves_per_cu_cap": shape[2],
-             "set_by": "--launch"} if args.launch else None
+             "beam_in_registers": shape[3], "set_by": "--launch"} if args.launch else None
     if not args.no_autotune and not args.launch:
         with torch.cuda.stream(stream):
-            wpb_t, hf_t, cw_t, tms = idx.autotune(Qs, k, ef)
-        shape = (wpb_t, hf_t, cw_t)
+            wpb_t, hf_t, cw_t, tms, beam_t = idx.autotune(Qs, k, ef)
+        shape = (wpb_t, hf_t, cw_t, beam_t)
         tuned = {"waves_per_workgroup": wpb_t, "hash_factor": hf_t, "resident_waves_per_cu_cap": cw_t,
-                 "median_call_ms": round(tms, 4)}
+                 "beam_in_registers": beam_t, "median_call_ms": round(tms, 4)}
         log(f"[bench] autotune: {tuned}")
     qps, ms_per_step, kern_ms, rot_ms = timed(plain)
     expansions = int(s[:, 0].sum())
@@ -262,7 +264,7 @@ def main():
         from paper_2411_12229_amd import learned_stop
         # the learned-stop searches, and both searches at 80,000 queries, run
         # without the residency cap (it was tuned for the plain search of this batch)
-        idx.set_launch(shape[0], shape[1], 0)
+        idx.set_launch(shape[0], shape[1], 0, shape[3])
         t0 = time.time()
         _, Qtr = synth.gen_data(synth.SIFT_LIKE, n=1, nq=20_000, qseed=synth.seed(synth.SIFT_LIKE, "train"))
         gt_tr, _ = synth.ground_truth(X, Qtr, k, device=dev)
@@ -405,7 +407,7 @@ def main():
     d_h = torch.empty((args.nq, k), dtype=torch.float32).pin_memory()
     use_ls = roofline["kernel"].endswith("learned stop")
     e2e_ef = ls_res["ef"] if use_ls else ef
-    idx.set_launch(shape[0], shape[1], 0 if use_ls else shape[2])  # the shape the value was timed with
+    idx.set_launch(shape[0], shape[1], 0 if use_ls else shape[2], shape[3])  # the shape the value was timed with
 
     def e2e():
         with torch.cuda.stream(stream):
@@ -433,7 +435,7 @@ def main():
     serving = None
     if not args.no_serve:
         serving = []
-        idx.set_launch(shape[0], shape[1], 0)  # batches of every size: no residency cap
+        idx.set_launch(shape[0], shape[1], 0, shape[3])  # batches of every size: no residency cap
         rng = np.random.default_rng(11)
         ef_classes = (max(ef // 2, 1), ef, 4 * ef)
         legs = [(r, False) for r in (50_000, 200_000, 1_000_000, 4_000_000)]
@@ -592,7 +594,8 @@ def ls_study(args, dev):
         """Recall and rate of the fixed beam ef, in the launch shape the autotuner picks for it."""
         if ef not in cache:
             with torch.cuda.stream(stream):
-                shape = idx.autotune(Qs, k, ef)[:3]
+                t = idx.autotune(Qs, k, ef)
+                shape = t[:3] + t[4:5]
                 ids, _, st = idx.search(Qs, k, ef, stats=True)
                 rec = synth.recall(ids.cpu().numpy(), gt, k)
                 q = rate(lambda: idx.search(Qs, k, ef))
@@ -623,7 +626,7 @@ def ls_study(args, dev):
             # the stop kernels use 8 wavefronts per workgroup and no residency cap; the hash
             # factor is the one the autotuner picked for the fixed beam of the same size
             shape = fixed(ls_ef)["launch"]
-            idx.set_launch(shape[0], shape[1], 0)
+            idx.set_launch(shape[0], shape[1], 0, shape[3])
             with torch.cuda.stream(stream):
                 feat, lab = learned_stop.collect(idx, Qtrain, gtrain, k, ls_ef, t_min, 4)
                 bits = learned_stop.export(learned_stop.train(feat, lab, epochs=6))

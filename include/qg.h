@@ -47,8 +47,10 @@ enum {
 enum {
   QG_SEARCH_NO_ME = 1,     /* "w/o ME" ablation (Sec. 4.2.3): a vertex enters the beam only on its first estimate
                               (plain search only: QG_EUNSUPPORTED with per-query k and ef or the learned stop) */
-  QG_SEARCH_SMALL_HASH = 2 /* test hook: shrink the on-chip visited set to 128 slots so that queries take the
+  QG_SEARCH_SMALL_HASH = 2, /* test hook: shrink the on-chip visited set to 128 slots so that queries take the
                               overflow path (results are identical by construction) */
+  QG_SEARCH_LDS_BEAM = 4    /* keep the beam in LDS for this call, as for beams above 128 entries, instead of in
+                              registers (results are identical by construction) */
 };
 
 /* Largest supported beam size and result count. */
@@ -182,20 +184,26 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
  * pass), then, for the fastest pair, caps of 24, 20 and 16 resident
  * wavefronts per compute unit against no cap (a batch only a little larger
  * than the resident query slots can finish sooner on fewer, less contended
- * slots).  The fastest setting is kept for later searches of this index.
- * Each setting is timed as the median of seven calls after one untimed call.
- * Results do not depend on the choice, only the speed.  Outputs (host,
- * nullable): the chosen wavefronts per workgroup, F, the cap (0 = none) and
- * the median time in ms of one qg_search_ex call in that setting.
+ * slots), then, for beams of at most 128 entries, the beam kept in LDS
+ * against the beam kept in registers.  The fastest setting is kept for later
+ * searches of this index.  Each setting is timed as the median of seven calls
+ * after one untimed call.  Results do not depend on the choice, only the
+ * speed.  Outputs (host, nullable): the chosen wavefronts per workgroup, F,
+ * the cap (0 = none), the beam storage (1 = registers where the beam size
+ * allows, 0 = LDS) and the median time in ms of one qg_search_ex call in that
+ * setting.
  * Synchronous; allocates and frees temporary outputs. */
 int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
-                int32_t *out_wpb, int32_t *out_hash_factor, int32_t *out_cu_waves, double *out_ms);
+                int32_t *out_wpb, int32_t *out_hash_factor, int32_t *out_cu_waves, int32_t *out_beam,
+                double *out_ms);
 
 /* Set the launch shape directly (as qg_autotune would): wavefronts per
- * workgroup (1, 2, 4 or 8), visited-hash factor F (2, 3 or 4) and the cap on
- * resident wavefronts per compute unit (0 = none, at most 64).  Results do
- * not depend on it.  QG_EINVAL for values outside these sets. */
-int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves);
+ * workgroup (1, 2, 4 or 8), visited-hash factor F (2, 3 or 4), the cap on
+ * resident wavefronts per compute unit (0 = none, at most 64) and the beam
+ * storage (1: in registers for beams of at most 128 entries, the default;
+ * 0: always in LDS).  Results do not depend on it.  QG_EINVAL for values
+ * outside these sets. */
+int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam);
 
 /* ---- Serving loop (continuous batching) ----------------------------------
  * A server owns `streams` slots over one index.  Each slot has its own

@@ -84,6 +84,7 @@ struct qg_index {
   int hash_factor = 3;
   int cu_waves = 0;  // cap on resident wavefronts per compute unit (0 = as many as fit)
   int cus = 256;     // compute units of the device (read at creation; sizes the persistent grid)
+  bool beam_regs = true;  // beams of at most 128 entries live in registers (else in LDS)
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev[2];  // pairs per kernel class
@@ -196,6 +197,7 @@ qg_index* make_view(const qg_index* base) {
   v->hash_factor = base->hash_factor;
   v->cu_waves = base->cu_waves;
   v->cus = base->cus;
+  v->beam_regs = base->beam_regs;
   v->fb_slots = base->fb_slots;
   v->fb_words = base->fb_words;
   if (hipMalloc(&v->counters, sizeof(int) * kCounters) != hipSuccess ||
@@ -490,7 +492,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   if (nq < 0) return fail(QG_EINVAL, "nq < 0");
   if (k <= 0 || ef <= 0) return fail(QG_EINVAL, "k and ef must be positive");
   if (k > QG_MAX_K || ef > QG_MAX_EF) return fail(QG_EUNSUPPORTED, "k or ef above the supported maximum");
-  if (flags & ~(QG_SEARCH_NO_ME | QG_SEARCH_SMALL_HASH)) return fail(QG_EINVAL, "unknown flags");
+  if (flags & ~(QG_SEARCH_NO_ME | QG_SEARCH_SMALL_HASH | QG_SEARCH_LDS_BEAM)) return fail(QG_EINVAL, "unknown flags");
   const bool no_me = flags & QG_SEARCH_NO_ME;
   if (no_me && (ef_q || stop)) return fail(QG_EUNSUPPORTED, "QG_SEARCH_NO_ME applies to the plain search only");
   if (stop) {
@@ -568,7 +570,8 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   while (wpb > 1 && (size_t)wpb * L.total + extra > lds_cap) wpb >>= 1;
   if ((size_t)L.total + extra > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
   const size_t lds = (size_t)wpb * L.total + extra;
-  int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, wpb, lds);
+  const int nb = (idx->beam_regs && !(flags & QG_SEARCH_LDS_BEAM)) ? qgk::beam_regs(false, ls, ef, idx->N) : 0;
+  int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, nb, wpb, lds);
   if (occ <= 0) occ = 1;
   if (idx->cu_waves > 0) occ = std::min(occ, std::max(1, idx->cu_waves / wpb));
   int64_t want = (nq + wpb - 1) / wpb;
@@ -581,10 +584,10 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
           "rotate queries");
   if (!fx && (rc = record(idx, 0, false))) return rc;
   if (!fx && (rc = record(idx, 1, true))) return rc;
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, a, grid, wpb, lds, idx->stream), "search");
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, nb, a, grid, wpb, lds, idx->stream), "search");
   if (!fx && (rc = record(idx, 1, false))) return rc;
   // overflow pass: one wavefront per workgroup, one bitset each
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, a, idx->fb_slots, 1, (size_t)Lf.total + extra, idx->stream),
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, 0, a, idx->fb_slots, 1, (size_t)Lf.total + extra, idx->stream),
           "search overflow pass");
   return QG_OK;
 }
@@ -613,7 +616,8 @@ int qg_search_mixed_stop(const qg_index* idx, const float* queries, int64_t nq, 
 }
 
 int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
-                int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, double* out_ms) {
+                int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam,
+                double* out_ms) {
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (nq <= 0 || !queries) return fail(QG_EINVAL, "autotuning needs queries");
   DeviceGuard g(idx->device);
@@ -621,7 +625,9 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
   float* dists = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int keep_wpb = idx->wpb_pref, keep_hf = idx->hash_factor, keep_cw = idx->cu_waves;
+  const bool keep_beam = idx->beam_regs;
   int best_wpb = keep_wpb, best_hf = keep_hf, best_cw = 0, rc = QG_OK;
+  bool best_beam = true;
   double best = -1.0;
   auto cleanup = [&]() {
     if (e0) (void)hipEventDestroy(e0);
@@ -657,6 +663,7 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
   // wavefronts per compute unit for that shape (a batch only slightly larger
   // than the resident slots can finish sooner with fewer, less contended slots)
   idx->cu_waves = 0;
+  idx->beam_regs = true;
   for (int wpb : {1, 2, 4, 8}) {
     for (int hf : {2, 3, 4}) {
       idx->wpb_pref = wpb;
@@ -686,23 +693,37 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
       }
     }
   }
+  if (!rc && qgk::beam_regs(false, 0, ef, idx->N) > 0) {  // the beam in LDS for the best shape
+    idx->cu_waves = best_cw;
+    idx->beam_regs = false;
+    double t;
+    time_it(t);
+    if (!rc && t < best) {
+      best = t;
+      best_beam = false;
+    }
+  }
   cleanup();
   idx->wpb_pref = rc ? keep_wpb : best_wpb;
   idx->hash_factor = rc ? keep_hf : best_hf;
   idx->cu_waves = rc ? keep_cw : best_cw;
+  idx->beam_regs = rc ? keep_beam : best_beam;
   if (rc) return rc;
   if (out_wpb) *out_wpb = best_wpb;
   if (out_hash_factor) *out_hash_factor = best_hf;
   if (out_cu_waves) *out_cu_waves = best_cw;
+  if (out_beam) *out_beam = best_beam ? 1 : 0;
   if (out_ms) *out_ms = best;
   return QG_OK;
 }
 
-int qg_set_launch(qg_index* idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves) {
+int qg_set_launch(qg_index* idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam) {
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(QG_EINVAL, "wavefronts per workgroup not 1, 2, 4 or 8");
   if (hash_factor < 2 || hash_factor > 4) return fail(QG_EINVAL, "hash factor not 2, 3 or 4");
   if (cu_waves < 0 || cu_waves > 64) return fail(QG_EINVAL, "resident wavefront cap out of range");
+  if (beam != 0 && beam != 1) return fail(QG_EINVAL, "beam storage not 0 (LDS) or 1 (registers)");
+  idx->beam_regs = beam == 1;
   idx->wpb_pref = wpb;
   idx->hash_factor = hash_factor;
   idx->cu_waves = cu_waves;

@@ -65,9 +65,12 @@ hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, con
 // 3 per-query k and ef (k_q, ef_q set), 4 per-query k and ef with the learned
 // stop (MLP staged in LDS, as for 1), 5 "w/o ME" (the hash holds estimated
 // vertices, not visited ones)
-hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const SearchArgs& a, int grid, int wpb,
-                         size_t lds, hipStream_t st);
-int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, size_t lds);
+// nb: beam registers per lane (0: beam in LDS; 1, 2: ef up to 64, 128), as
+// beam_regs() picks for the pass, mode, bound on ef and vector count.
+int beam_regs(bool overflow_pass, int ls_mode, int ef_bound, int64_t n);
+hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, int nb, const SearchArgs& a, int grid,
+                         int wpb, size_t lds, hipStream_t st);
+int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int nb, int wpb, size_t lds);
 constexpr size_t mlp_lds_bytes() { return 2 * 64 * 16 + 8 * 64 * 16 + 3 * 128 + 16; }
 hipError_t launch_estimate(int D, int R, const EstimateArgs& a, int64_t nq, hipStream_t st);
 

@@ -44,6 +44,10 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kChecked = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;
+// Register-resident beams also flag entries whose vertex has been expanded
+// through another entry (consumed duplicates); ids then take 30 bits.
+constexpr uint32_t kDup = 0x40000000u;
+constexpr uint32_t kIdMask30 = 0x3fffffffu;
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -523,6 +527,22 @@ __device__ __forceinline__ bool visited_insert(const Visited& v, uint32_t id, in
   }
 }
 
+// Insert id (wave-uniform), known to be absent, into the LDS hash: the first
+// empty slot of its probe sequence, found by one read of 64 consecutive slots.
+__device__ __forceinline__ void visited_add_absent(const Visited& v, uint32_t id, int lane) {
+  uint32_t base = v.slot0(id);
+  for (;;) {
+    const uint32_t s = (base + lane) & v.mask;
+    const uint64_t em = ballot(v.tab[s] == kEmpty);
+    if (em) {
+      if (lane == first_lane(em)) v.tab[s] = id;
+      break;
+    }
+    base += 64;
+  }
+  wave_sync();
+}
+
 // Per-lane insert into the set of estimated vertices (w/o ME); true if id was
 // absent, so this lane's estimate is its first.  Lanes holding the same id see
 // exactly one true.  The LDS table must keep an empty slot for every lane that
@@ -713,6 +733,16 @@ __device__ __forceinline__ float stop_mlp_lds(const uint8_t* m, float f, int lan
 
 __device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
   return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
+}
+
+// Element r (wave-uniform) of a small register array, by selects (no dynamic
+// register indexing).
+template <int NB>
+__device__ __forceinline__ uint64_t pick(const uint64_t (&b)[NB], int r) {
+  uint64_t v = b[0];
+#pragma unroll
+  for (int i = 1; i < NB; ++i) v = r == i ? b[i] : v;
+  return v;
 }
 
 template <int D, int R, bool GV, int LS>
@@ -1185,6 +1215,404 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
   }
 }
 
+// Algorithm 1 with the beam in registers (ef up to 64 NB): lane i holds beam
+// entries i and 64 + i, each with a checked flag and a consumed-duplicate flag
+// (its vertex was expanded through another entry).  The loop is
+// software-pipelined.  The next vertex to expand is known before the merge:
+// it is the smaller of the best new candidate and the first old entry neither
+// checked nor consumed.  Its block is prefetched, and at the top of the next
+// iteration its exact distance, FastScan lookups and visited probes are issued
+// while the previous merge's read-back is still in flight; the pop's
+// bookkeeping (flags, pop count, the next unconsumed entry) then runs on the
+// merged beam.  Results and counters equal those of search_one.
+template <int D, int R, int LS, int NB>
+__device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L,
+                              const uint8_t* mlp) {
+  using BV = BlockView<D, R>;
+  constexpr int DPL = BV::DPL;
+  constexpr int LPN = BV::LPN;
+  constexpr uint64_t kNone = ~0ull;  // sorts after every real entry
+  constexpr uint64_t kFlags = (uint64_t)(kChecked | kDup);
+  const int lane = lane_id();
+  int ef = a.ef, k = a.k;
+  if constexpr (is_mixed<LS>) {
+    ef = uni(a.ef_q[q]);
+    k = uni(a.k_q[q]);
+    if (k < 1 || k > a.k || ef < 1 || ef > a.ef) {  // rejected: an all-padding row, stats[3] = -1
+      for (int i = lane; i < a.k_out; i += 64) {
+        a.out_ids[q * a.k_out + i] = -1;
+        a.out_dists[q * a.k_out + i] = __builtin_inff();
+      }
+      if (a.out_stats && lane < 4) a.out_stats[4 * q + lane] = lane == 3 ? -1 : 0;
+      return;
+    }
+  }
+  int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
+  uint64_t* sc = reinterpret_cast<uint64_t*>(lds + L.beam);    // merge output range (ef_cap words)
+  uint64_t* cbuf = reinterpret_cast<uint64_t*>(lds + L.cand);  // candidates (R + 4 words)
+  float* nkey = reinterpret_cast<float*>(lds + L.nkey);
+  uint32_t* nid = reinterpret_cast<uint32_t*>(lds + L.nid);
+  Visited vis;
+  vis.tab = reinterpret_cast<uint32_t*>(lds + L.hash);
+  vis.hbits = a.hash_bits;
+  vis.mask = (1u << a.hash_bits) - 1u;
+  vis.bits = nullptr;
+  const int vis_limit = (1 << a.hash_bits) / 2;
+  for (int i = lane; i < (1 << a.hash_bits); i += 64) vis.tab[i] = kEmpty;
+
+  constexpr bool kQvLds = qgl::query_in_lds(D);
+  float qv[kQvLds ? 1 : DPL];
+  float* qs = reinterpret_cast<float*>(lds + L.qv);
+  const float* qr = a.queries + q * D;
+  if constexpr (kQvLds) {
+    for (int i = lane; i < D; i += 64) qs[i] = qr[i];
+  } else {
+#pragma unroll
+    for (int t = 0; t < DPL; ++t) {
+      const int i = lane + 64 * t;
+      qv[t] = (i < D) ? qr[i] : 0.0f;
+    }
+  }
+  auto dist = [&](const float(&xv)[DPL]) {
+    if constexpr (kQvLds) {
+      float pp = 0.0f;
+#pragma unroll
+      for (int t = 0; t < DPL; ++t) {
+        const float d = qs[lane + 64 * t] - xv[t];
+        pp = __builtin_fmaf(d, d, pp);
+      }
+      return butterfly_f(pp);
+    } else {
+      return exact_dist<DPL>(qv, xv);
+    }
+  };
+  const float delta = build_lut<D, R>(a.qrot + q * D, lut);
+
+  // the entry starts the beam, keyed by its exact distance; it is the first
+  // vertex expanded, so its block serves both
+  BV b;
+  b.load(a.blocks + (int64_t)a.entry * a.block_bytes, lane);
+  float dp = uni(dist(b.x));
+  const float de = dp;
+  uint32_t p = (uint32_t)a.entry;
+  uint64_t pword = pack_kv(de, p);  // p's beam word
+  uint64_t tail = pword;            // beam[ef - 1] whenever the beam is full
+  uint64_t bw[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) bw[r] = (r == 0 && lane == 0) ? pword : kNone;
+  int size = 1;
+  bool pending = false;  // a merge whose read-back has not been done yet
+  int pend_nv = 0;       // its number of candidates
+  int nvis = 0, nnc = 0, expansions = 0, pops = 0, appended = 0, since = 0;
+  float nn_wk = 0.0f;
+  uint32_t nn_wi = 0;
+  const bool nn_in_regs = k <= 64;
+  float nrk = 0.0f;
+  uint32_t nri = 0;
+  BV nxt;
+
+  for (;;) {
+    // ---- expansion of p (block b, exact distance dp)
+    // read-back of the pending merge's range, into the beam registers (their
+    // old values died with the merge's scatter)
+    if (pending) {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const int i = 64 * r + lane;
+        bw[r] = i < size ? sc[i] : kNone;
+      }
+    }
+    // visited probes: p's insertion run (64 consecutive slots) and each
+    // neighbour's first slot (p itself is excluded explicitly: it is inserted
+    // below, after these reads)
+    const uint32_t pslot = vis.slot0(p);
+    const uint32_t prun = vis.tab[(pslot + lane) & vis.mask];
+    const uint32_t nb = (uint32_t)b.nb;
+    const bool probe = (lane % LPN == 0) && b.nb >= 0 && nb != p;
+    uint32_t ns = vis.slot0(probe ? nb : 0u);
+    uint32_t ne = vis.tab[ns];
+    // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
+    const int S = b.fastscan(lut, lane);
+    // finish the pending merge: range slots still holding the sentinel take
+    // the candidates in rank order
+    if (pending) {
+      int holes = 0;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const bool hole = 64 * r + lane < size && bw[r] == kNone;
+        const uint64_t hm = ballot(hole);
+        if (hole) bw[r] = cbuf[holes + lanes_below(hm)];
+        holes += __popcll(hm);
+      }
+      if (size == ef) tail = rdlane64(pick<NB>(bw, (ef - 1) >> 6), (ef - 1) & 63) & ~kFlags;
+    }
+    const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
+    const uint64_t cand = pack_kv(est, nb);
+
+    // pop p: its entry is the first entry neither checked nor consumed; the
+    // unchecked entries before it are consumed duplicates, each a pop
+    uint64_t um[NB], pm[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      um[r] = ballot(!((uint32_t)bw[r] & kChecked));
+      pm[r] = ballot(bw[r] == pword);
+    }
+    int rs = NB - 1, f = 0;
+#pragma unroll
+    for (int r = NB - 1; r >= 0; --r)
+      if (pm[r]) {
+        rs = r;
+        f = first_lane(pm[r]);
+      }
+    const uint64_t before = (1ull << f) - 1ull;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const uint64_t dup = r < rs ? um[r] : (r == rs ? (um[r] & before) : 0ull);
+      pops += __popcll(dup);
+      const uint64_t take = dup | (r == rs ? 1ull << f : 0ull);
+      if ((take >> lane) & 1ull) bw[r] |= kChecked;
+    }
+    ++pops;
+    // p's other unchecked entries become consumed duplicates; the next
+    // unconsumed entry (o2f, a prefetch candidate) and the next unchecked one
+    // (o2u, for the stop features) follow p's entry
+    uint64_t o2f = kNone, o2u = kNone;
+    {
+      int rf = -1, ru = -1;
+      uint64_t mf = 0, mu = 0;
+#pragma unroll
+      for (int r = NB - 1; r >= 0; --r) {
+        const uint32_t lo = (uint32_t)bw[r];
+        if ((lo & (kChecked | kDup | kIdMask30)) == p) bw[r] |= kDup;
+        const uint64_t fr_ = ballot(!((uint32_t)bw[r] & (kChecked | kDup)));
+        const uint64_t ur_ = ballot(!((uint32_t)bw[r] & kChecked));
+        if (fr_) {
+          rf = r;
+          mf = fr_;
+        }
+        if (ur_) {
+          ru = r;
+          mu = ur_;
+        }
+      }
+      if (rf >= 0) o2f = rdlane64(pick<NB>(bw, rf), first_lane(mf)) & ~kFlags;
+      if (has_stop<LS> && ru >= 0) o2u = rdlane64(pick<NB>(bw, ru), first_lane(mu)) & ~kFlags;
+    }
+
+    // insert p into the visited set: the first empty slot of its probe run
+    {
+      uint64_t em = ballot(prun == kEmpty);
+      if (em) {
+        if (lane == first_lane(em)) vis.tab[(pslot + lane) & vis.mask] = p;
+      } else {
+        visited_add_absent(vis, p, lane);  // 64 occupied slots in a row (the table is at most half full)
+      }
+    }
+    if (++nvis > vis_limit) {  // on-chip visited set full: hand the query to the overflow path
+      if (lane == 0) {
+        const int slot = atomicAdd(a.counters + 1, 1);
+        a.overflow_list[slot] = (int32_t)q;
+      }
+      return;
+    }
+    ++expansions;
+
+    // visited filter: continue the probes that met another id
+    bool seen = probe && ne == nb;
+    bool more = probe && ne != nb && ne != kEmpty;
+    while (ballot(more)) {
+      if (more) {
+        ns = (ns + 1) & vis.mask;
+        ne = vis.tab[ns];
+        seen = ne == nb;
+        more = ne != nb && ne != kEmpty;
+      }
+    }
+    bool valid = probe && !seen;
+    const int app = uni((int)__popcll(ballot(valid)));
+    appended += app;
+    if (size == ef) valid = valid && cand < tail;  // would fall past the cut anyway
+    const uint64_t V = ballot(valid);
+    const int nv = uni((int)__popcll(V));
+    if (nv > 0) {  // compacted for the merge's broadcast reads (after the read-back above: LDS keeps order)
+      if (valid) cbuf[lanes_below(V)] = cand;
+      if (lane < 4) cbuf[nv + lane] = kNone;  // padding: below no entry, no candidate
+    }
+
+    // best candidate (the smallest (estimate, id) among them)
+    uint64_t best = kNone;
+    if (nv > 0) {
+      const uint32_t hk = wave_min_u32(valid ? (uint32_t)(cand >> 32) : 0xFFFFFFFFu);
+      const uint64_t tie = ballot(valid && (uint32_t)(cand >> 32) == hk);
+      const uint32_t lo = (tie & (tie - 1)) ? wave_min_u32((tie >> lane) & 1 ? (uint32_t)cand : 0xFFFFFFFFu)
+                                            : rdlane((uint32_t)cand, first_lane(tie));
+      best = ((uint64_t)hk << 32) | lo;
+    }
+    // the next vertex to expand: prefetch its block (Sec. 3.1.4)
+    const uint64_t nxt_f = best < o2f ? best : o2f;
+    if (nxt_f != kNone) nxt.load(a.blocks + (int64_t)((uint32_t)nxt_f & kIdMask30) * a.block_bytes, lane);
+    const uint64_t nxt_u = best < o2u ? best : o2u;
+    const float bfk = nxt_u == kNone ? __builtin_inff() : unsortable((uint32_t)(nxt_u >> 32));
+
+    // implicit re-ranking: NN keeps the k smallest (distance, id) seen
+    ++since;
+    if (nnc < k || kv_less(dp, p, nn_wk, nn_wi)) {
+      since = 0;
+      if (nn_in_regs) {
+        const int pos = (int)__popcll(ballot(lane < nnc && kv_less(nrk, nri, dp, p)));
+        const int last = nnc < k ? nnc : k - 1;
+        const float upk = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(nrk), 0x138, 0xF, 0xF, false));
+        const uint32_t upi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nri, 0x138, 0xF, 0xF, false);
+        if (lane > pos && lane <= last) {
+          nrk = upk;
+          nri = upi;
+        }
+        if (lane == pos) {
+          nrk = dp;
+          nri = p;
+        }
+        nnc = nnc < k ? nnc + 1 : k;
+        if (nnc == k) {
+          nn_wk = rdlane(nrk, k - 1);
+          nn_wi = rdlane(nri, k - 1);
+        }
+      } else {
+        int pos = 0;
+        for (int base = 0; base < nnc; base += 64) {
+          const int i = base + lane;
+          const bool lt = (i < nnc) && kv_less(nkey[i < nnc ? i : 0], nid[i < nnc ? i : 0], dp, p);
+          pos += __popcll(ballot(lt));
+        }
+        const int last = nnc < k ? nnc : k - 1;  // entries [pos, last) move up by one
+        for (int base = ((last - 1) >> 6) << 6; base >= 0 && last > pos; base -= 64) {
+          const int i = base + lane;
+          float kk = 0.0f;
+          uint32_t ii = 0;
+          const bool mv = (i >= pos) && (i < last);
+          if (mv) {
+            kk = nkey[i];
+            ii = nid[i];
+          }
+          wave_sync();
+          if (mv) {
+            nkey[i + 1] = kk;
+            nid[i + 1] = ii;
+          }
+          wave_sync();
+          if (base < pos) break;
+        }
+        pos = uni(pos);
+        nkey[pos] = dp;
+        nid[pos] = p;
+        wave_sync();
+        nnc = nnc < k ? nnc + 1 : k;
+        if (nnc == k) {
+          nn_wk = uni(nkey[k - 1]);
+          nn_wi = uni(nid[k - 1]);
+        }
+      }
+    }
+
+    // Merge, truncated to ef (its read-back happens at the top of the next
+    // iteration).  Every old entry counts the candidates below it (cnt) and
+    // every candidate its rank among them, from broadcast reads of the
+    // compacted candidates.  The new range is filled with a sentinel, old
+    // entry i is written at i + cnt_i and the candidates by rank to the
+    // candidate array; the range slots still holding the sentinel are then the
+    // candidates' places in rank order (an old entry equal to a candidate
+    // precedes it, since cnt counts strictly smaller candidates).
+    pending = nv > 0;
+    if (nv > 0) {
+      uint64_t bm[NB];
+      int cnt[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        bm[r] = bw[r] & ~kFlags;
+        cnt[r] = 0;
+      }
+      int rank = 0;
+      const int nv4 = (nv + 3) & ~3;
+      for (int t = 0; t < nv4; t += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint64_t ct = cbuf[t + u];
+#pragma unroll
+          for (int r = 0; r < NB; ++r) cnt[r] += ct < bm[r];
+          rank += ct < cand;
+        }
+      }
+      const int nsz = (size + nv < ef) ? size + nv : ef;
+#pragma unroll
+      for (int r = 0; r < NB; ++r)
+        if (64 * r + lane < nsz) sc[64 * r + lane] = kNone;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        const int np = 64 * r + lane + cnt[r];
+        if (64 * r + lane < size && np < ef) sc[np] = bw[r];
+      }
+      if (valid) cbuf[rank] = cand;  // after the count loop's reads (LDS keeps order)
+      size = nsz;
+      pend_nv = nv;
+    }
+
+    if constexpr (has_stop<LS>) {
+      if (expansions >= a.ls_t_min && (expansions - a.ls_t_min) % a.ls_t_every == 0) {
+        StopFeatures F;
+        const float nn1 = nn_in_regs ? rdlane(nrk, 0) : uni(nkey[0]);
+        const float nnk = nn_in_regs ? rdlane(nrk, nnc - 1) : uni(nkey[nnc - 1]);
+        F.compute(expansions, pops, nnc, k, since, de, nn1, nnk, bfk, size, ef, dp, app, R);
+        float out;
+        if constexpr (mlp_in_lds<LS>)
+          out = stop_mlp_lds(mlp, F.mine, lane, reinterpret_cast<float*>(lds + L.aux));
+        else
+          out = a.ls_w ? stop_mlp(a.ls_w, F, lane) : __builtin_nanf("");
+        if (out > a.ls_theta) break;  // false for NaN: no model, no stop
+      }
+    }
+
+    if (nxt_f == kNone) {
+      // no unconsumed entry is left (and no candidate, so no merge): every
+      // remaining unchecked entry is a consumed duplicate, popped in turn
+#pragma unroll
+      for (int r = 0; r < NB; ++r) pops += __popcll(ballot(!((uint32_t)bw[r] & kChecked)));
+      break;
+    }
+    p = (uint32_t)nxt_f & kIdMask30;
+    pword = nxt_f;
+    b = nxt;
+    dp = uni(dist(b.x));
+  }
+  (void)pend_nv;
+
+  // answer: NN ascending by (distance, id), padded with (-1, inf)
+  const int k_out = is_mixed<LS> ? a.k_out : k;
+  for (int i = lane; i < k_out; i += 64) {
+    int32_t id = -1;
+    float d = __builtin_inff();
+    if (i < nnc) {
+      id = nn_in_regs ? (int32_t)nri : (int32_t)nid[i];
+      d = nn_in_regs ? nrk : nkey[i];
+    }
+    a.out_ids[q * k_out + i] = id;
+    a.out_dists[q * k_out + i] = d;
+  }
+  if (a.out_stats && lane == 0) {
+    int32_t* st = a.out_stats + 4 * q;
+    st[0] = expansions;
+    st[1] = pops;
+    st[2] = appended;
+    st[3] = 0;
+  }
+}
+
+// Minimum wavefronts per SIMD the register allocator must allow: 8 (64
+// VGPRs) for the narrow plain kernels with R = 32 and the beam in registers,
+// 6 for the narrow stop-only and mixed-batch kernels.
+template <int D, int R, int LS, int NB>
+constexpr int waves_hint() {
+  return D > 256 || NB > 0 ? 1 : (mlp_in_lds<LS> || LS == kMixed) ? 6 : 1;
+}
+
 // Each wavefront takes queries from a shared counter until none is left.
 // GV = false: main pass over all queries with the LDS visited hash.
 // GV = true : overflow pass over the queries the main pass handed over, with
@@ -1193,8 +1621,8 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // For the narrow shapes the stop-only and mixed-batch kernels hold their
 // registers to 80, so that 6 wavefronts per SIMD fit (LDS sets residency for
 // the stop-only kernels anyway).
-template <int D, int R, bool GV, int LS>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((mlp_in_lds<LS> || LS == kMixed) && D <= 256 ? 6 : 1))) void search_kernel(
+template <int D, int R, bool GV, int LS, int NB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_hint<D, R, LS, NB>()))) void search_kernel(
     SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
@@ -1217,7 +1645,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((mlp_in_lds
     qi = __builtin_amdgcn_readlane(qi, 0);
     if (qi >= limit) break;
     const int64_t q = GV ? (int64_t)a.overflow_list[qi] : (int64_t)qi;
-    search_one<D, R, GV, LS>(a, q, lds, L, gbits, mlp);
+    if constexpr (NB > 0)
+      search_one_rb<D, R, LS, NB>(a, q, lds, L, mlp);
+    else
+      search_one<D, R, GV, LS>(a, q, lds, L, gbits, mlp);
   }
 }
 
@@ -1278,9 +1709,9 @@ hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, con
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV, int LS>
+template <int D, int R, bool GV, int LS, int NB>
 static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t lds, hipStream_t st) {
-  auto kern = search_kernel<D, R, GV, LS>;
+  auto kern = search_kernel<D, R, GV, LS, NB>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1290,10 +1721,10 @@ static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV, int LS>
+template <int D, int R, bool GV, int LS, int NB>
 static int occupancy_t(int wpb, size_t lds) {
   int nb = 0;
-  auto kern = search_kernel<D, R, GV, LS>;
+  auto kern = search_kernel<D, R, GV, LS, NB>;
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -1301,48 +1732,83 @@ static int occupancy_t(int wpb, size_t lds) {
   return nb;
 }
 
-hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, const SearchArgs& a, int grid, int wpb,
-                         size_t lds, hipStream_t st) {
-#define QG_LS(d, r, gv)                                                             \
-  switch (ls_mode) {                                                                \
-    case kLsOff: return launch_search_t<d, r, gv, kLsOff>(a, grid, wpb, lds, st);     \
-    case kLsStop: return launch_search_t<d, r, gv, kLsStop>(a, grid, wpb, lds, st);   \
-    case kLsTrace: return launch_search_t<d, r, gv, kLsTrace>(a, grid, wpb, lds, st); \
-    case kMixed: return launch_search_t<d, r, gv, kMixed>(a, grid, wpb, lds, st);     \
-    case kMixedStop: return launch_search_t<d, r, gv, kMixedStop>(a, grid, wpb, lds, st); \
-    case kNoMe: return launch_search_t<d, r, gv, kNoMe>(a, grid, wpb, lds, st);         \
-    default: return hipErrorInvalidValue;                                           \
+struct LaunchOp {
+  const SearchArgs* a;
+  int grid, wpb;
+  size_t lds;
+  hipStream_t st;
+  template <int D, int R, bool GV, int LS, int NB>
+  hipError_t run() const {
+    return launch_search_t<D, R, GV, LS, NB>(*a, grid, wpb, lds, st);
   }
-#define QG_CASE(d, r)                  \
-  if (D == d && R == r) {              \
-    if (overflow_pass) QG_LS(d, r, true) \
-    QG_LS(d, r, false)                 \
+};
+
+struct OccupancyOp {
+  int wpb;
+  size_t lds;
+  template <int D, int R, bool GV, int LS, int NB>
+  int run() const {
+    return occupancy_t<D, R, GV, LS, NB>(wpb, lds);
   }
+};
+
+// The kernel instantiation for (D, R), pass, mode and beam storage.  Register
+// beams (nb 1, 2) exist for the main pass of the plain, stop-only and mixed
+// modes; the traced, "w/o ME" and overflow-pass kernels keep the beam in LDS.
+template <int D, int R, class Op, class Ret>
+static Ret dispatch_mode(bool gv, int ls, int nb, const Op& op, Ret bad) {
+  if (gv) {
+    switch (ls) {
+      case kLsOff: return op.template run<D, R, true, kLsOff, 0>();
+      case kLsStop: return op.template run<D, R, true, kLsStop, 0>();
+      case kLsTrace: return op.template run<D, R, true, kLsTrace, 0>();
+      case kMixed: return op.template run<D, R, true, kMixed, 0>();
+      case kMixedStop: return op.template run<D, R, true, kMixedStop, 0>();
+      case kNoMe: return op.template run<D, R, true, kNoMe, 0>();
+      default: return bad;
+    }
+  }
+#define QG_NB(ls_)                                                                  \
+  (nb == 1 ? op.template run<D, R, false, ls_, 1>()                                 \
+           : nb == 2 ? op.template run<D, R, false, ls_, 2>() : op.template run<D, R, false, ls_, 0>())
+  switch (ls) {
+    case kLsOff: return QG_NB(kLsOff);
+    case kLsStop: return QG_NB(kLsStop);
+    case kLsTrace: return op.template run<D, R, false, kLsTrace, 0>();
+    case kMixed: return QG_NB(kMixed);
+    case kMixedStop: return QG_NB(kMixedStop);
+    case kNoMe: return op.template run<D, R, false, kNoMe, 0>();
+    default: return bad;
+  }
+#undef QG_NB
+}
+
+// Measured on the SIFT-shaped 1M x 128 index (10,000 queries): one beam
+// register is 11-14% faster than the LDS beam in the plain, mixed and
+// stop-only kernels; two registers tie with it in the plain and mixed kernels
+// and lose 6% in the stop-only kernel (whose MLP already holds many registers).
+int beam_regs(bool overflow_pass, int ls_mode, int ef_bound, int64_t n) {
+  if (overflow_pass || ls_mode == kLsTrace || ls_mode == kNoMe || n > (int64_t)kIdMask30) return 0;
+  if (ef_bound <= 64) return 1;
+  return (ef_bound <= 128 && (ls_mode == kLsOff || ls_mode == kMixed)) ? 2 : 0;
+}
+
+hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, int nb, const SearchArgs& a, int grid,
+                         int wpb, size_t lds, hipStream_t st) {
+  const LaunchOp op{&a, grid, wpb, lds, st};
+#define QG_CASE(d, r) \
+  if (D == d && R == r) return dispatch_mode<d, r>(overflow_pass, ls_mode, nb, op, hipErrorInvalidValue);
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
-#undef QG_LS
   return hipErrorInvalidValue;
 }
 
-int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int wpb, size_t lds) {
-#define QG_LS(d, r, gv)                                                   \
-  switch (ls_mode) {                                                      \
-    case kLsOff: return occupancy_t<d, r, gv, kLsOff>(wpb, lds);            \
-    case kLsStop: return occupancy_t<d, r, gv, kLsStop>(wpb, lds);          \
-    case kLsTrace: return occupancy_t<d, r, gv, kLsTrace>(wpb, lds);        \
-    case kMixed: return occupancy_t<d, r, gv, kMixed>(wpb, lds);            \
-    case kMixedStop: return occupancy_t<d, r, gv, kMixedStop>(wpb, lds);    \
-    case kNoMe: return occupancy_t<d, r, gv, kNoMe>(wpb, lds);              \
-    default: return 0;                                                    \
-  }
-#define QG_CASE(d, r)                  \
-  if (D == d && R == r) {              \
-    if (overflow_pass) QG_LS(d, r, true) \
-    QG_LS(d, r, false)                 \
-  }
+int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int nb, int wpb, size_t lds) {
+  const OccupancyOp op{wpb, lds};
+#define QG_CASE(d, r) \
+  if (D == d && R == r) return dispatch_mode<d, r>(overflow_pass, ls_mode, nb, op, 0);
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
-#undef QG_LS
   return 0;
 }
 

@@ -24,7 +24,7 @@ __host__ __device__ constexpr int off_nbr(int D, int R) { return off_fadd(D, R) 
 // Per-wavefront LDS of the search kernel (bytes).  ef_cap and k_cap are
 // multiples of 4 so every piece stays 16-byte aligned.
 struct SearchLds {
-  int lut, beam, cand, hash, nkey, nid, qv, total;
+  int lut, beam, cand, hash, nkey, nid, qv, aux, total;
 };
 
 __host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
@@ -40,7 +40,8 @@ __host__ __device__ constexpr int lut_rows_padded(int D, int R) { return D / 4 +
 // cand: one expansion's candidates (R words + 4 of padding), reused for their
 // insertion points; beam: packed (key, id | checked) words kept sorted; hash:
 // visited ids; nkey/nid: the k nearest vertices found so far; qv: the raw
-// query when D > 256.  The pieces
+// query when D > 256; aux: 256 bytes through which the learned stop's MLP
+// passes its features and first hidden layer.  The pieces
 // indexed by lane (LUT, candidates, beam) come first, at offsets fixed by D
 // and R, so one address register serves them with immediate offsets.
 __host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int hash_cap, int k_cap) {
@@ -53,6 +54,7 @@ __host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int ha
   s.nkey = o;  o += 4 * k_cap;
   s.nid = o;   o += 4 * k_cap;
   s.qv = o;    o += query_in_lds(D) ? 4 * D : 0;
+  s.aux = o;   o += 256;
   s.total = o;
   return s;
 }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libqg.so")
 QG_OK, QG_EINVAL, QG_ENOMEM, QG_EIO, QG_EFORMAT, QG_EDEVICE, QG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 QG_SEARCH_NO_ME = 1
 QG_SEARCH_SMALL_HASH = 2
+QG_SEARCH_LDS_BEAM = 4
 QG_NOALLOC_SCRATCH_BYTES = 16 << 20
 QG_MAX_EF = 2048
 QG_MAX_K = 1024
@@ -63,9 +64,9 @@ def _load():
         "qg_copy_blocks": ([P, i64, i64, P], c_int),
         "qg_set_stream": ([P, P], c_int),
         "qg_reserve": ([P, i64], c_int),
-        "qg_set_launch": ([P, i32, i32, i32], c_int),
+        "qg_set_launch": ([P, i32, i32, i32, i32], c_int),
         "qg_autotune": ([P, P, i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
-                         ctypes.POINTER(ctypes.c_double)], c_int),
+                         ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
         "qg_index_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)], c_int),
         "qg_timing": ([P, c_int], c_int),
@@ -138,16 +139,16 @@ class Index:
 
     def autotune(self, queries: torch.Tensor, k: int, ef: int, flags: int = 0):
         """Pick the launch shape (wavefronts per workgroup, visited-hash factor, cap on resident
-        wavefronts per compute unit) by timing searches of these queries; returns
-        (wpb, hash_factor, cu_waves (0 = no cap), best ms per call)."""
-        w, h, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        wavefronts per compute unit, beam storage) by timing searches of these queries; returns
+        (wpb, hash_factor, cu_waves (0 = no cap), best ms per call, beam (1 = registers, 0 = LDS))."""
+        w, h, c, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(_lib.qg_autotune(self._h, _dev(queries, torch.float32, "queries"), queries.shape[0], k, ef, flags,
-                                ctypes.byref(w), ctypes.byref(h), ctypes.byref(c), ctypes.byref(ms)))
-        return w.value, h.value, c.value, ms.value
+                                ctypes.byref(w), ctypes.byref(h), ctypes.byref(c), ctypes.byref(b), ctypes.byref(ms)))
+        return w.value, h.value, c.value, ms.value, b.value
 
-    def set_launch(self, wpb: int, hash_factor: int, cu_waves: int = 0) -> None:
+    def set_launch(self, wpb: int, hash_factor: int, cu_waves: int = 0, beam: int = 1) -> None:
         """Set the launch shape directly (the values qg_autotune picks)."""
-        _check(_lib.qg_set_launch(self._h, int(wpb), int(hash_factor), int(cu_waves)))
+        _check(_lib.qg_set_launch(self._h, int(wpb), int(hash_factor), int(cu_waves), int(beam)))
 
     def reserve(self, nq: int) -> None:
         """Size the query scratch for batches of up to nq queries (before capturing graphs)."""

@@ -264,3 +264,55 @@ def test_deterministic_batch_independent_and_stream(cfg1):
     st.synchronize()
     c["idx"].set_stream(None)
     assert np.array_equal(ids.cpu().numpy(), a[0])
+
+
+@pytest.mark.parametrize("k,ef", [(1, 1), (10, 5), (10, 48), (10, 64), (10, 65), (100, 100), (64, 128), (10, 129)])
+def test_beam_storage_parity(cfg1, k, ef):
+    """Beams of at most 128 entries run with the beam in registers (one or two
+    words per lane, the pipelined loop) unless QG_SEARCH_LDS_BEAM keeps it in
+    LDS; both must equal the oracle in ids, distances and counters, at the
+    edges of each storage (1, 64, 65, 128, 129 entries)."""
+    c = cfg1
+    Q = np.concatenate([c["Q"], c["Q"] + 0.05])
+    say(f"beam storage k={k} ef={ef}")
+    orc = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], Q, k, ef, with_stats=True)
+    _assert_same(_search(c["idx"], Q, k, ef), orc, f"registers k={k} ef={ef}")
+    _assert_same(_search(c["idx"], Q, k, ef, flags=qg.QG_SEARCH_LDS_BEAM), orc, f"LDS k={k} ef={ef}")
+
+
+def test_beam_storage_mixed_and_stop(cfg1):
+    """The mixed-batch, stop-only and mixed-with-stop kernels also run with the
+    register beam below 129 entries; each row equals the oracle's search (or
+    stopped search) at its own k and ef, with either storage."""
+    c = cfg1
+    rng = np.random.default_rng(41)
+    Q = np.concatenate([c["Q"], c["Q"] + 0.05])
+    n = len(Q)
+    ks = rng.choice([1, 10, 20], n).astype(np.int32)
+    efs = rng.choice([8, 40, 64, 100], n).astype(np.int32)
+    w = ((rng.standard_normal(qg.QG_STOP_MLP_PARAMS) * 0.3).astype(np.float32).view(np.uint32) >> 16)
+    w = w.astype(np.uint16)
+    wd = torch.from_numpy(w.view(np.int16)).to(DEV)
+    _, _, _, (_, _, oo, oc) = oracle.search_ls(c["blocks"], 128, 32, c["e"], c["M"], Q, 10, 64, w=w, theta=np.inf,
+                                               t_min=4, t_every=2, max_evals=128)
+    theta = float(np.quantile(np.concatenate([oo[i, :oc[i]] for i in range(n)]), 0.7))
+    say(f"beam storage: mixed and stop kernels, theta={theta:.4f}")
+    for flags in (0, qg.QG_SEARCH_LDS_BEAM):
+        gi, gd, gs = c["idx"].search_mixed(T(Q), T(ks), T(efs), k_max=20, ef_max=100, flags=flags, stats=True)
+        si, sd, ss, _ = c["idx"].search_stop(T(Q), 10, 64, wd, theta=theta, t_min=4, t_every=2, flags=flags,
+                                              stats=True)
+        mi, md, ms_ = c["idx"].search_mixed_stop(T(Q), T(ks), T(efs), wd, theta, t_min=4, t_every=2, k_max=20,
+                                                 ef_max=100, flags=flags, stats=True)
+        torch.cuda.synchronize()
+        gi, gd, gs = gi.cpu().numpy(), gd.cpu().numpy(), gs.cpu().numpy()
+        mi, md, ms_ = mi.cpu().numpy(), md.cpu().numpy(), ms_.cpu().numpy()
+        oi, od, ost, _ = oracle.search_ls(c["blocks"], 128, 32, c["e"], c["M"], Q, 10, 64, w=w, theta=theta,
+                                          t_min=4, t_every=2)
+        _assert_same((si.cpu().numpy(), sd.cpu().numpy(), ss.cpu().numpy()), (oi, od, ost), f"stop flags={flags}")
+        for k, ef in set(zip(ks.tolist(), efs.tolist())):
+            sel = np.nonzero((ks == k) & (efs == ef))[0]
+            o = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], Q[sel], k, ef, with_stats=True)
+            _assert_same((gi[sel, :k], gd[sel, :k], gs[sel]), o, f"mixed k={k} ef={ef} flags={flags}")
+            o2 = oracle.search_ls(c["blocks"], 128, 32, c["e"], c["M"], Q[sel], k, ef, w=w, theta=theta, t_min=4,
+                                  t_every=2)
+            _assert_same((mi[sel, :k], md[sel, :k], ms_[sel]), o2[:3], f"mixed stop k={k} ef={ef} flags={flags}")
