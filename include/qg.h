@@ -78,6 +78,38 @@ int qg_load_index(const char *path, int device, qg_index **out);
 int qg_build_index(const float *vectors, int64_t n, int32_t d, const int32_t *graph, int32_t r,
                    const float *rotation, int32_t entry, int device, qg_index **out);
 
+/* Flags of qg_build_graph. */
+enum {
+  QG_GRAPH_REFINE = 1, /* supplement edges to exactly r per vertex (Sec. 3.2.2), random fill when too few */
+  QG_GRAPH_REPAIR = 2  /* link vertices unreachable from the entry (an addition: clustered data can leave the
+                          graph disconnected) */
+};
+
+/* Algorithm 2 (Indexing, Sec. 3.2) on `device`: starting from init_graph[n][r]
+ * (distinct non-self ids, as a random initial graph), `iters` times: encode
+ * the current graph (the FastScan data of every vertex), run Algorithm 1 for
+ * every vector with beam ef_build and ef_build results (the search kernels of
+ * qg_search_ex), take as candidates of u the results other than u together
+ * with u's current neighbours, and keep by the NSG rule (Sec. 3.2.1: scan the
+ * candidates by (distance, id) and keep v unless a kept w is closer to v than
+ * u is; at most r); all lists are replaced at once.  With QG_GRAPH_REFINE a
+ * vertex left with fewer than r neighbours then takes the pruned candidates
+ * that survive the largest angle threshold leaving enough of them (Sec.
+ * 3.2.2: a candidate is pruned when a closer candidate makes an angle below
+ * the threshold with it at u; the limit of the paper's binary search is taken
+ * exactly), nearest first, and ids from fill[n][r] while still short.  With
+ * QG_GRAPH_REPAIR every vertex unreachable from `entry` is then linked from
+ * its nearest reachable vertex.  Distances, norms and inner products are fp64
+ * sums over dimensions in ascending order.  vectors[n][d], rotation[d][d],
+ * init_graph, fill (needed with QG_GRAPH_REFINE) and out_graph[n][r] (int32,
+ * -1 = empty slot) are device arrays; out_stats (host, nullable) receives
+ * [vertices reachable before the repair, repairs made, reachable after,
+ * elapsed microseconds].  Synchronous; allocates its working memory (about
+ * n (12 (ef_build + r) + 8 r) bytes). */
+int qg_build_graph(const float *vectors, int64_t n, int32_t d, int32_t r, int32_t ef_build, int32_t iters,
+                   const float *rotation, int32_t entry, const int32_t *init_graph, const int32_t *fill,
+                   int32_t flags, int device, int32_t *out_graph, int64_t *out_stats);
+
 /* Write the index to a file in the format read by qg_load_index. Synchronous. */
 int qg_save_index(const qg_index *idx, const char *path);
 

@@ -42,6 +42,11 @@ static int cmp_cand(const void *a, const void *b) {
   return (x->id > y->id) - (x->id < y->id);
 }
 
+static int cmp_i64(const void *a, const void *b) {
+  int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+  return (x > y) - (x < y);
+}
+
 static int cmp_dbl(const void *a, const void *b) {
   double x = *(const double *)a, y = *(const double *)b;
   return (x > y) - (x < y);
@@ -151,9 +156,10 @@ static int64_t bfs(const int32_t *G, int64_t N, int R, int32_t entry, char *seen
  *    minus u itself;
  *  - "adjust G" replaces every list at once after all vertices are pruned;
  *  - refinement (line 9) runs on the last iteration's candidates;
- *  - an addition: vertices unreachable from the entry are linked from their
- *    nearest reachable vertex (its empty slot, else its farthest edge) until
- *    all are reachable, since clustered inputs can leave disconnected parts.
+ *  - an addition: vertices unreachable from the entry are linked, in rounds,
+ *    from the nearest reachable vertex their search finds (its empty slot,
+ *    else its farthest edge), since the NSG rule leaves vertices that no list
+ *    keeps (in-degree 0) and clustered inputs can leave disconnected parts.
  * stats (nullable): [reachable before repair, repairs made, reachable after].
  * opts: bit 0 = refine; bits 8.. = thread count. */
 int qgo_build_graph(const float *X, int64_t N, int D, int R, int EF, int t, const float *M, int32_t entry,
@@ -228,53 +234,96 @@ int qgo_build_graph(const float *X, int64_t N, int D, int R, int EF, int t, cons
     }
   }
 
-  /* connectivity repair (an addition to the paper) */
+  /* Connectivity repair (an addition; Sec. 3.2 has none), in rounds.  A round
+   * finds the vertices unreachable from the entry (breadth first).  Each such v
+   * runs Algorithm 1 on the current graph (beam EF, EF results) and picks the
+   * nearest result that still has a slot not taken by an earlier repair (every
+   * result was visited from the entry, hence is reachable).  Then, per picked
+   * vertex w in increasing id, its v's in increasing id take w's empty slots
+   * (in slot order), then w's edges not taken by a repair, farthest first
+   * (fp64, ties to the larger id), while such slots are left.  The next round
+   * starts from the new graph, until every vertex is reachable or a round
+   * links none. */
   char *seen = (char *)malloc((size_t)N);
   int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
   int64_t repairs = 0;
   char *fixed = (char *)calloc((size_t)(N * R), 1); /* edges added by the repair are never overwritten */
+  int32_t *unr = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  int64_t *pick = (int64_t *)malloc(sizeof(int64_t) * (size_t)N); /* (w << 32) | v, sorted below */
+  cand_t *slots = (cand_t *)malloc(sizeof(cand_t) * (size_t)R);
   if (stats) stats[0] = bfs(G, N, R, entry, seen, queue);
-  for (int64_t guard = 0; guard < N; ++guard) {
+  for (int round = 0; round < 64; ++round) {
     if (bfs(G, N, R, entry, seen, queue) == N) break;
-    ++repairs;
-    int64_t v = 0;
-    while (seen[v]) ++v;
-    const float *xv = X + v * D;
-    /* nearest reachable vertex (fp64, ties to the lower id) that still has a
-     * slot not taken by an earlier repair */
-    int64_t w = -1;
-    double bw = INFINITY;
-    for (int64_t u = 0; u < N; ++u) {
-      if (!seen[u]) continue;
-      int free_slot = 0;
-      for (int j = 0; j < R && !free_slot; ++j) free_slot = !fixed[u * R + j];
-      if (!free_slot) continue;
-      double d = dist2(X + u * D, xv, D);
-      if (d < bw) {
-        bw = d;
-        w = u;
-      }
-    }
-    if (w < 0) break;
-    int32_t *row = G + w * R;
-    int slot = -1;
-    for (int j = 0; j < R && slot < 0; ++j)
-      if (row[j] < 0) slot = j;
-    if (slot < 0) { /* the farthest edge not added by a repair */
-      double far = -1.0;
-      for (int j = 0; j < R; ++j) {
-        if (fixed[w * R + j]) continue;
-        double d = dist2(X + w * D, X + (int64_t)row[j] * D, D);
-        if (slot < 0 || d > far || (d == far && row[j] > row[slot])) {
-          far = d;
-          slot = j;
+    int64_t nu = 0;
+    for (int64_t v = 0; v < N; ++v)
+      if (!seen[v]) unr[nu++] = (int32_t)v;
+    if (qgo_encode(X, N, D, G, R, M, blocks, nthreads) != 0) return -3;
+#pragma omp parallel
+    {
+      int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)EF);
+      float *dd = (float *)malloc(sizeof(float) * (size_t)EF);
+#pragma omp for schedule(dynamic, 16)
+      for (int64_t a = 0; a < nu; ++a) {
+        const int32_t v = unr[a];
+        qgo_search(blocks, N, D, R, entry, M, X + (int64_t)v * D, 1, EF, EF, 0, ids, dd, NULL, 1);
+        int64_t w = -1;
+        for (int b = 0; b < EF && w < 0 && ids[b] >= 0; ++b) {
+          int free_slot = 0;
+          for (int j = 0; j < R && !free_slot; ++j) free_slot = !fixed[(int64_t)ids[b] * R + j];
+          if (free_slot) w = ids[b];
         }
+        pick[a] = w < 0 ? -1 : (int64_t)((uint64_t)w << 32 | (uint32_t)v);
+      }
+      free(ids);
+      free(dd);
+    }
+    qsort(pick, (size_t)nu, sizeof(int64_t), cmp_i64);
+    int64_t made = 0;
+    for (int64_t a = 0; a < nu;) {
+      if (pick[a] < 0) {
+        ++a;
+        continue;
+      }
+      const int64_t w = pick[a] >> 32;
+      int32_t *row = G + w * R;
+      int ns = 0;
+      for (int j = 0; j < R; ++j)
+        if (row[j] < 0) {
+          slots[ns].d = INFINITY; /* empty slots first, in slot order */
+          slots[ns++].id = j;
+        }
+      const int nempty = ns;
+      for (int j = 0; j < R; ++j)
+        if (row[j] >= 0 && !fixed[w * R + j]) {
+          slots[ns].d = dist2(X + w * D, X + (int64_t)row[j] * D, D);
+          slots[ns++].id = j;
+        }
+      for (int i = nempty + 1; i < ns; ++i) { /* farthest first, ties to the larger neighbour id */
+        cand_t x = slots[i];
+        int pos = i;
+        while (pos > nempty && (slots[pos - 1].d < x.d ||
+                                (slots[pos - 1].d == x.d && row[slots[pos - 1].id] < row[x.id]))) {
+          slots[pos] = slots[pos - 1];
+          --pos;
+        }
+        slots[pos] = x;
+      }
+      int next = 0;
+      for (; a < nu && pick[a] >= 0 && (pick[a] >> 32) == w; ++a) {
+        if (next >= ns) continue; /* no slot left: this v waits for the next round */
+        const int j = slots[next++].id;
+        row[j] = (int32_t)(pick[a] & 0xffffffff);
+        fixed[w * R + j] = 1;
+        ++repairs;
+        ++made;
       }
     }
-    row[slot] = (int32_t)v;
-    fixed[w * R + slot] = 1;
+    if (!made) break;
   }
   free(fixed);
+  free(unr);
+  free(pick);
+  free(slots);
   int64_t reach = bfs(G, N, R, entry, seen, queue);
   if (stats) {
     stats[1] = repairs;

@@ -9,9 +9,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqg.so")
-SOURCES = [os.path.join(CSRC, "qg_kernels.hip"), os.path.join(CSRC, "qg_api.cpp"), os.path.join(CSRC, "qg_server.cpp")]
-HEADERS = [os.path.join(CSRC, "qg_kernels.h"), os.path.join(CSRC, "qg_layout.h"), os.path.join(CSRC, "qg_internal.h"),
-           os.path.join(ROOT, "include", "qg.h")]
+SOURCES = [os.path.join(CSRC, f) for f in ("qg_kernels.hip", "qg_graph.hip", "qg_api.cpp", "qg_graph.cpp",
+                                            "qg_server.cpp")]
+HEADERS = [os.path.join(CSRC, f) for f in ("qg_kernels.h", "qg_graph.h", "qg_layout.h", "qg_internal.h")] + [
+    os.path.join(ROOT, "include", "qg.h")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -20,6 +20,8 @@ QG_OK, QG_EINVAL, QG_ENOMEM, QG_EIO, QG_EFORMAT, QG_EDEVICE, QG_EUNSUPPORTED = 0
 QG_SEARCH_NO_ME = 1
 QG_SEARCH_SMALL_HASH = 2
 QG_SEARCH_LDS_BEAM = 4
+QG_GRAPH_REFINE = 1
+QG_GRAPH_REPAIR = 2
 QG_NOALLOC_SCRATCH_BYTES = 16 << 20
 QG_MAX_EF = 2048
 QG_MAX_K = 1024
@@ -52,6 +54,7 @@ def _load():
     sig = {
         "qg_load_index": ([ctypes.c_char_p, c_int, PP], c_int),
         "qg_build_index": ([P, i64, i32, P, i32, P, i32, c_int, PP], c_int),
+        "qg_build_graph": ([P, i64, i32, i32, i32, i32, P, i32, P, P, i32, c_int, P, ctypes.POINTER(i64)], c_int),
         "qg_save_index": ([P, ctypes.c_char_p], c_int),
         "qg_search": ([P, P, i64, i32, i32, P, P], c_int),
         "qg_search_ex": ([P, P, i64, i32, i32, i32, P, P, P], c_int),
@@ -271,6 +274,21 @@ def qg_load_index(path: str, device: int = 0) -> Index:
     h = ctypes.c_void_p()
     _check(_lib.qg_load_index(path.encode(), device, ctypes.byref(h)))
     return Index(h, device)
+
+
+def qg_build_graph(vectors: torch.Tensor, r: int, ef_build: int, iters: int, rotation: torch.Tensor, entry: int,
+                   init_graph: torch.Tensor, fill: torch.Tensor | None, refine: bool = True, repair: bool = True):
+    """Algorithm 2 on the vectors' device -> (graph int32 [n, r] on the device, stats dict)."""
+    n, d = vectors.shape
+    out = torch.empty((n, r), dtype=torch.int32, device=vectors.device)
+    st = (ctypes.c_int64 * 4)()
+    flags = (QG_GRAPH_REFINE if refine else 0) | (QG_GRAPH_REPAIR if repair else 0)
+    _check(_lib.qg_build_graph(_dev(vectors, torch.float32, "vectors"), n, d, r, ef_build, iters,
+                               _dev(rotation, torch.float32, "rotation"), int(entry),
+                               _dev(init_graph, torch.int32, "init_graph"),
+                               _dev(fill, torch.int32, "fill") if fill is not None else None, flags,
+                               vectors.device.index or 0, _dev(out, torch.int32, "out_graph"), st))
+    return out, dict(zip(("reach_before_repair", "repairs", "reach_after_repair", "microseconds"), list(st)))
 
 
 def qg_build_index(vectors: torch.Tensor, graph: torch.Tensor, rotation: torch.Tensor, entry: int) -> Index:
