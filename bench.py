@@ -44,6 +44,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def make_graph(c, X, M, entry, dev, kind, build_ef=400, build_iters=3):
+    """The index graph of config c: Algorithm 2 (Sec. 3.2) on the GPU from a seeded random initial graph and
+    seeded fill ids, or the k-NN + random links input generator.  Returns (G int32 [N, R] on the host, info)."""
+    import torch
+
+    import synth
+    from paper_2411_12229_amd import qg
+
+    R = synth.CONFIGS[c].R
+    N = X.shape[0]
+    t0 = time.time()
+    if kind == "knn":
+        G = synth.knn_graph(X, R, synth.seed(c, "long"), device=dev)
+        info = {"graph": "k-NN + random long links (input generator)", "build_s": round(time.time() - t0, 1)}
+    else:
+        G0 = torch.from_numpy(synth.random_graph(N, R, synth.seed(c, "graph"))).to(dev)
+        fill = torch.from_numpy(synth.random_graph(N, R, synth.seed(c, "fill"))).to(dev)
+        t1 = time.time()
+        Gd, st = qg.qg_build_graph(torch.from_numpy(X).to(dev), R, build_ef, build_iters,
+                                   torch.from_numpy(M).to(dev), entry, G0, fill)
+        torch.cuda.synchronize()
+        G = Gd.cpu().numpy()
+        info = {"graph": f"Algorithm 2 on the GPU (EF={build_ef}, t={build_iters}, refinement to R={R}, "
+                         f"connectivity repair)", "build_s": round(time.time() - t1, 2),
+                "build_device_s": round(st["microseconds"] / 1e6, 2), "repairs": st["repairs"],
+                "reachable_before_repair": st["reach_before_repair"]}
+    log(f"[bench] graph: {info}")
+    return G, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,7 +97,14 @@ def main():
                     help="wpb,hash_factor,cu_waves[,beam]: set this launch shape (beam 1: in registers where the "
                          "beam size allows, the default; 0: in LDS) for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
-    ap.add_argument("--no-ablation", action="store_true", help="skip the w/o ME leg")
+    ap.add_argument("--ablation", action="store_true", help="also sweep the w/o ME ablation (Sec. 4.2.3)")
+    ap.add_argument("--no-ablation", action="store_true", help=argparse.SUPPRESS)  # the ablation is opt-in
+    ap.add_argument("--graph", default="alg2", choices=("alg2", "knn"),
+                    help="index graph: Algorithm 2 built on the GPU (the paper's index), or k-NN + random links")
+    ap.add_argument("--build-ef", type=int, default=400, help="Algorithm 2 beam EF (Sec. 4.1: 400)")
+    ap.add_argument("--build-iters", type=int, default=3, help="Algorithm 2 iterations t (Sec. 4.1: 3)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the recall curve of the other graph (k-NN + random links) beside the bench's")
     ap.add_argument("--ablation-ef", default="",
                     help="comma-separated beam sizes of the w/o ME leg (default: 16,32,48,64,96,128,192 and the "
                          "bench's own)")
@@ -100,6 +137,7 @@ def main():
         _, Q = synth.gen_data(synth.SIFT_LIKE, n=1, nq=args.nq)  # queries do not depend on n
         idx = qg.qg_load_index(args.load_index)
         X = G = M = entry = gt = None
+        graph_info = {"graph": "loaded from " + args.load_index}
         Qd = torch.from_numpy(Q).to(dev)
         log(f"[bench] loaded {args.load_index}: {idx.n} blocks")
     else:
@@ -107,10 +145,8 @@ def main():
         X, Q = synth.gen_data(synth.SIFT_LIKE, n=args.n, nq=args.nq)
         M = synth.rotation(D, synth.seed(synth.SIFT_LIKE, "rotation"))
         log(f"[bench] data {X.shape} queries {Q.shape} in {time.time() - t0:.1f}s")
-        t0 = time.time()
-        G = synth.knn_graph(X, R, synth.seed(synth.SIFT_LIKE, "long"), device=dev)
         entry = synth.medoid(X)
-        log(f"[bench] input graph (k-NN + random links) in {time.time() - t0:.1f}s; entry {entry}")
+        G, graph_info = make_graph(synth.SIFT_LIKE, X, M, entry, dev, args.graph, args.build_ef, args.build_iters)
         Xd, Gd, Md, Qd = (torch.from_numpy(a).to(dev) for a in (X, G, M, Q))
         t0 = time.time()
         idx = qg.qg_build_index(Xd, Gd, Md, entry)
@@ -235,7 +271,7 @@ def main():
     # the "w/o ME" ablation (Sec. 4.2.3): a vertex enters the beam only on its
     # first estimate; recall and rate against the beam size, beside the sweep
     no_me = None
-    if not args.no_ablation:
+    if args.ablation:
         no_me = []
         ablation_efs = ({int(x) for x in args.ablation_ef.split(",")} if args.ablation_ef
                         else {16, 32, 48, 64, ef, 96, 128, 192})
@@ -304,6 +340,34 @@ def main():
                         f"{got[1]:.4f}, {tms / nl:.4f} ms per 4000 queries")
                     if best_ls is None or tms / nl < best_ls[0]:
                         best_ls = (tms / nl, te, got, ls_ef_c, bits_c)
+        # the fixed beam picked the same way as the stop: the smallest beam (grid, then steps of
+        # 4) whose recall on the same held-out queries reaches the target plus the same margin
+        def ho_recall(e):
+            with torch.cuda.stream(stream):
+                i_h, _ = idx.search(Qth, k, e)
+            stream.synchronize()
+            return learned_stop.recall_rows(i_h, gt_th).mean().item()
+        ef_ho, lo_ho = None, None
+        for e in EFS:
+            if ho_recall(e) >= args.target + 0.005:
+                ef_ho = e
+                break
+            lo_ho = e
+        if ef_ho is not None and lo_ho is not None:
+            for e in range(lo_ho + 4, ef_ho, 4):
+                if ho_recall(e) >= args.target + 0.005:
+                    ef_ho = e
+                    break
+        fixed_ho = None
+        if ef_ho is not None:
+            with torch.cuda.stream(stream):
+                i_t, _, st_t = idx.search(Qs, k, ef_ho, stats=True)
+            stream.synchronize()
+            q_ho, ms_ho, kern_ho, _ = timed(lambda: idx.search(Qs, k, ef_ho))
+            fixed_ho = {"ef": ef_ho, "recall@10": round(synth.recall(i_t.cpu().numpy(), gt, k), 4),
+                        "qps": round(q_ho, 1), "kernel_ms": round(kern_ho, 4),
+                        "mean_expansions": round(st_t[:, 0].float().mean().item(), 2)}
+            log(f"[bench] fixed beam picked on the held-out queries: {fixed_ho}")
         pick = best_ls[2] if best_ls is not None else None
         if best_ls is not None:
             t_every, ls_ef, bits = best_ls[1], best_ls[3], best_ls[4]
@@ -324,7 +388,11 @@ def main():
             ls_res = {"ef": ls_ef, "theta": theta, "t_min": t_min, "t_every": t_every, "recall@10": round(rec_l, 4),
                       "qps": round(qps_l, 1), "ms_per_step": round(ms_l, 4), "kernel_ms": round(kern_l, 4),
                       "mean_expansions": round(exp_l / args.nq, 2), "trace_points": feat_points,
-                      "train_queries": 16_000, "theta_queries": 4_000}
+                      "train_queries": 16_000, "theta_queries": 4_000,
+                      "fixed_ef_picked_on_held_out": fixed_ho,
+                      "comparison": "learned stop (ef, spacing, theta) and fixed_ef_picked_on_held_out are both "
+                                    "chosen on the same 4,000 held-out queries with recall target + 0.005, then "
+                                    "run on the test queries"}
             log(f"[bench] learned stop ef={ls_ef} theta={theta}: recall@10={rec_l:.4f} {qps_l:,.0f} q/s "
                 f"(fixed ef={ef}: recall {rec:.4f} {qps:,.0f} q/s)")
             # the same two searches on 8 copies of the batch (80,000 queries): there
@@ -475,6 +543,33 @@ def main():
             serving.append(row)
             log(f"[bench] serving {rate:,}/s offered: {row}")
 
+    # the recall curve of the other graph on the same data and queries
+    other = None
+    if not args.no_compare and X is not None and args.graph == "alg2":
+        Gk, info_k = make_graph(synth.SIFT_LIKE, X, M, entry, dev, "knn")
+        idx_k = qg.qg_build_index(torch.from_numpy(X).to(dev), torch.from_numpy(Gk).to(dev),
+                                  torch.from_numpy(M).to(dev), entry)
+        idx_k.set_stream(stream)
+        idx_k.set_launch(shape[0], shape[1], shape[2], shape[3])
+        curve = []
+        for e in (16, 24, 32, 48, 64, 68, 96, 128):
+            with torch.cuda.stream(stream):
+                i_k, _, st_k = idx_k.search(Qs, k, e, stats=True)
+            stream.synchronize()
+            idx_k.timing(True)
+            with torch.cuda.stream(stream):
+                for _ in range(3):
+                    idx_k.search(Qs, k, e)
+            stream.synchronize()
+            idx_k.timing(False)
+            nl, tms = idx_k.timing_read(1)
+            curve.append({"ef": e, "recall@10": round(synth.recall(i_k.cpu().numpy(), gt, k), 4),
+                          "mean_expansions": round(st_k[:, 0].float().mean().item(), 2),
+                          "kernel_qps": round(args.nq / (tms / nl / 1e3), 1)})
+            log(f"[bench] k-NN graph ef={e}: {curve[-1]}")
+        idx_k.free()
+        other = {"graph": info_k["graph"], "launch": list(shape), "sweep": curve}
+
     cpu = None
     if not args.no_cpu and X is not None:
         sys.path.insert(0, os.path.join(ROOT, "oracle"))
@@ -525,7 +620,7 @@ def main():
                                f"with recall@10 >= {args.target}",
                    "n": args.n, "d": D, "r": R, "nq": args.nq, "k": k,
                    "search": "learned-stop" if roofline["kernel"].endswith("learned stop") else "fixed-ef",
-                   "graph": "k-NN + random long links (input generator)"},
+                   **graph_info},
         "fixed_ef": fixed,
         "learned_stop": ls_res,
         "end_to_end_qps_with_pcie": round(e2e_qps, 1),
@@ -537,6 +632,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "other_graph": other,
         "without_me": {"what": "the w/o ME ablation of Sec. 4.2.3 on the same index and queries, same launch shape; "
                                "compare with sweep (multiple estimates)", "sweep": no_me} if no_me else None,
     }
@@ -560,8 +656,8 @@ def ls_study(args, dev):
     t0 = time.time()
     X, Q = synth.gen_data(c)
     M = synth.rotation(D, synth.seed(c, "rotation"))
-    G = synth.knn_graph(X, R, synth.seed(c, "long"), device=dev)
     entry = synth.medoid(X)
+    G, ginfo = make_graph(c, X, M, entry, dev, args.graph, args.build_ef, args.build_iters)
     idx = qg.qg_build_index(torch.from_numpy(X).to(dev), torch.from_numpy(G).to(dev), torch.from_numpy(M).to(dev),
                             entry)
     gt, _ = synth.ground_truth(X, Q, k, device=dev)
@@ -604,8 +700,29 @@ def ls_study(args, dev):
             log(f"[ls-study] fixed ef={ef}: {cache[ef]}")
         return cache[ef]
 
+    def heldout_recall(ef):
+        with torch.cuda.stream(stream):
+            ids, _ = idx.search(Qth, k, ef)
+        stream.synchronize()
+        return learned_stop.recall_rows(ids, gth).mean().item()
+
     t_min, rows = 8, []
     for target in (0.90, 0.95, 0.99):
+        margin = min(0.005, 0.2 * (1.0 - target))
+        # the fixed beam picked like the stop's settings: on the held-out queries, with the same margin
+        ho = None
+        lo_h = None
+        for ef in EFS:
+            if heldout_recall(ef) >= target + margin:
+                ho = ef
+                break
+            lo_h = ef
+        if ho is not None and lo_h is not None:
+            for ef in range(lo_h + 4, ho, 4):
+                if heldout_recall(ef) >= target + margin:
+                    ho = ef
+                    break
+        fx_ho = fixed(ho) if ho is not None else None
         lo, hi = None, None
         for ef in EFS:
             if fixed(ef)["recall@10"] >= target:
@@ -613,7 +730,7 @@ def ls_study(args, dev):
                 break
             lo = ef
         if hi is None:
-            rows.append({"target": target, "fixed": None, "learned_stop": None})
+            rows.append({"target": target, "fixed": None, "fixed_picked_on_held_out": fx_ho, "learned_stop": None})
             continue
         if lo is not None:
             for ef in range(lo + 4, hi, 4):  # the same refinement as the bench line's
@@ -633,8 +750,7 @@ def ls_study(args, dev):
                 for te in (4, 8):
                     # theta is picked on held-out queries with a margin: 0.005, or a fifth of the
                     # missing recall when that is smaller (0.002 at 0.99)
-                    got = learned_stop.pick_theta(idx, Qth, gth, bits, k, ls_ef, t_min, te,
-                                                  target=target + min(0.005, 0.2 * (1.0 - target)))
+                    got = learned_stop.pick_theta(idx, Qth, gth, bits, k, ls_ef, t_min, te, target=target + margin)
                     if got is None:
                         continue
                     ids, _, st, _ = idx.search_stop(Qs, k, ls_ef, bits, theta=got[0], t_min=t_min, t_every=te,
@@ -645,14 +761,19 @@ def ls_study(args, dev):
                            "qps": round(q, 1), "mean_expansions": round(st[:, 0].float().mean().item(), 2),
                            "trace_points": int(feat.shape[0])}
                     log(f"[ls-study] target {target} learned stop: {row}")
-                    if rec >= target and (best is None or q > best["qps"]):
+                    if best is None or q > best["qps"]:
                         best = row
-        rows.append({"target": target, "fixed": fx, "learned_stop": best,
-                     "speedup": round(best["qps"] / fx["qps"], 3) if best else None})
+        rows.append({"target": target, "fixed": fx, "fixed_picked_on_held_out": fx_ho, "learned_stop": best,
+                     "speedup_vs_held_out_fixed": round(best["qps"] / fx_ho["qps"], 3) if best and fx_ho else None,
+                     "speedup_vs_test_tuned_fixed": round(best["qps"] / fx["qps"], 3) if best else None})
     wl = ("SIFT-shaped 1M x 128" if c == synth.SIFT_LIKE else
           "1M x 768 unit-norm rank-128 + noise, queries from a mean-shifted copy")
-    print(json.dumps({"study": "learned stop vs fixed ef", "workload": wl + ", R=32 k-NN + random links, "
-                      f"{len(Q)} queries, k=10",
+    print(json.dumps({"study": "learned stop vs fixed ef", "workload": wl + f", R={R}, {len(Q)} queries, k=10",
+                      **ginfo,
+                      "selection": "fixed_picked_on_held_out and learned_stop are both chosen on the same 4,000 "
+                                   "held-out queries (recall target plus the same margin), then run on the test "
+                                   "queries; fixed is the smallest beam reaching the target on the test queries "
+                                   "themselves (the usual curve point)",
                       "n_gpus": 1, "steps": args.steps, "train_queries": 16_000, "theta_queries": 4_000,
                       "rows": rows}), flush=True)
 
