@@ -428,15 +428,14 @@ def main():
                                  "expansions_per_launch": exp_l, "kernel_ms": round(kern_l, 4)})
 
     # HBM traffic from the committed PMC measurement (FETCH_SIZE and WRITE_SIZE
-    # scaled by a plain copy), only while the kernel source and ef still match
+    # scaled by a plain copy), only while the kernel source, graph and ef still match
     try:
-        import hashlib
         with open(os.path.join(ROOT, "profiles", "search_kernel_traffic.json")) as f:
             tr = json.load(f)
         src = os.path.join(ROOT, "paper_2411_12229_amd", "csrc", "qg_kernels.hip")
         sha = kernel_code_hash(src)
         if tr.get("kernel_source_sha256_prefix") == sha and tr.get("ef") == ef and args.nq == 10_000 \
-                and args.n == 1_000_000:
+                and args.n == 1_000_000 and tr.get("graph") == args.graph:
             roofline["traffic"] = tr["traffic_bytes"]
     except (OSError, ValueError, KeyError):
         pass
