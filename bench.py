@@ -63,7 +63,7 @@ def make_graph(c, X, M, entry, dev, kind, build_ef=400, build_iters=3):
         fill = torch.from_numpy(synth.random_graph(N, R, synth.seed(c, "fill"))).to(dev)
         t1 = time.time()
         Gd, st = qg.qg_build_graph(torch.from_numpy(X).to(dev), R, build_ef, build_iters,
-                                   torch.from_numpy(M).to(dev), entry, G0, fill)
+                                   torch.from_numpy(M).to(dev), entry, G0, fill, progress=True)
         torch.cuda.synchronize()
         G = Gd.cpu().numpy()
         info = {"graph": f"Algorithm 2 on the GPU (EF={build_ef}, t={build_iters}, refinement to R={R}, "
@@ -111,6 +111,10 @@ def main():
     ap.add_argument("--ls-study", action="store_true",
                     help="instead of the benchmark line: learned stop against fixed ef at recall@10 0.90 / 0.95 / "
                          "0.99 (one JSON line)")
+    ap.add_argument("--workload", default="sift", choices=("sift", "gist960"),
+                    help="gist960: the 1M x 960 leg (R=64, k=10 and k=100, uneven beams in one mixed launch); "
+                         "prints its own JSON line")
+    ap.add_argument("--ls-targets", default="0.90,0.95,0.99", help="recall@10 targets of --ls-study")
     ap.add_argument("--ls-workload", default="sift", choices=("sift", "unit768"),
                     help="workload of --ls-study: the SIFT-shaped benchmark set or 1M x 768 unit-norm")
     ap.add_argument("--copy-probe", action="store_true",
@@ -129,6 +133,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.ls_study:
         return ls_study(args, dev)
+    if args.workload == "gist960":
+        return gist_leg(args, dev)
     cfg = synth.CONFIGS[synth.SIFT_LIKE]
     D, R, k = cfg.D, cfg.R, cfg.k
     if args.load_index:
@@ -638,6 +644,133 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def gist_leg(args, dev):
+    """GIST-shaped 1M x 960 (rank-64 non-negative factor model plus noise), R = 64, 1,000 queries: recall and
+    throughput of fixed beams at k = 10 and k = 100, each in the launch shape the autotuner picks for it, then
+    one mixed launch in which every query has its own (k, ef), autotuned for mixed batches, against the same
+    queries run as one plain launch per (k, ef) class.  Inputs resident on the device; search calls timed by
+    host clock over --steps calls and the search kernel by HIP events on the library's stream.  Parity at this
+    size is sampled in the tests (the oracle's encoding of all 1M blocks alone takes minutes of host time)."""
+    import torch
+
+    import synth
+    from paper_2411_12229_amd import qg
+
+    c = synth.GIST_LIKE
+    cfg = synth.CONFIGS[c]
+    D, R = cfg.D, cfg.R
+    t0 = time.time()
+    X, Q = synth.gen_data(c)
+    nq = len(Q)
+    M = synth.rotation(D, synth.seed(c, "rotation"))
+    entry = synth.medoid(X)
+    log(f"[gist] data {X.shape} and {nq} queries in {time.time() - t0:.1f}s")
+    G, ginfo = make_graph(c, X, M, entry, dev, args.graph, args.build_ef, args.build_iters)
+    idx = qg.qg_build_index(torch.from_numpy(X).to(dev), torch.from_numpy(G).to(dev), torch.from_numpy(M).to(dev),
+                            entry)
+    gt, _ = synth.ground_truth(X, Q, 100, device=dev)
+    del G, X
+    log(f"[gist] index and ground truth ready at {time.time() - t0:.1f}s")
+    stream = torch.cuda.Stream()
+    idx.set_stream(stream)
+    with torch.cuda.stream(stream):
+        Qs = torch.from_numpy(Q).to(dev)
+    stream.synchronize()
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        stream.synchronize()
+        idx.timing(True)
+        t1 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(args.steps):
+                fn()
+        stream.synchronize()
+        t2 = time.perf_counter()
+        idx.timing(False)
+        nl, kms = idx.timing_read(1)
+        return (t2 - t1) * 1e3 / args.steps, kms / max(nl, 1)
+
+    def fixed(k, ef):
+        with torch.cuda.stream(stream):
+            w, h, cw, _, beam = idx.autotune(Qs, k, ef)
+            ids, _, st = idx.search(Qs, k, ef, stats=True)
+        stream.synchronize()
+        rec = synth.recall(ids.cpu().numpy(), gt[:, :k], k)
+        ms, kms = timed(lambda: idx.search(Qs, k, ef))
+        E = int(st[:, 0].sum().item())
+        row = {"k": k, "ef": ef, f"recall@{k}": round(rec, 4), "qps": round(nq / ms * 1e3, 1),
+               "ms_per_call": round(ms, 4), "kernel_ms": round(kms, 4), "mean_expansions": round(E / nq, 2),
+               "kernel_gbps": round((E * idx.block_bytes + nq * (4 * D + 8 * k)) / (kms * 1e-3) / 1e9, 1),
+               "launch": [w, h, cw, beam]}
+        log(f"[gist] fixed {row}")
+        return row, rec
+
+    out = {"k10": [], "k100": []}
+    pick = {}
+    for k, grid in ((10, (16, 32, 48, 64, 96, 128, 192, 256)), (100, (100, 128, 160, 192, 256, 384, 512))):
+        for target in (0.95, 0.99):
+            pick.setdefault((k, target), None)
+        for ef in grid:
+            row, rec = fixed(k, ef)
+            out[f"k{k}"].append(row)
+            for target in (0.95, 0.99):
+                if pick[(k, target)] is None and rec >= target:
+                    pick[(k, target)] = ef
+            if rec >= 0.99:
+                break
+    # the mixed batch: each query draws one of four classes -- k = 10 or 100, at the beam that reaches
+    # recall 0.95 or 0.99 for that k (the largest grid beam where a target was not reached)
+    classes = []
+    for k in (10, 100):
+        for target in (0.95, 0.99):
+            ef = pick[(k, target)] or out[f"k{k}"][-1]["ef"]
+            classes.append((k, ef))
+    rng = np.random.default_rng(synth.seed(c, "queries"))
+    cls = rng.integers(0, len(classes), nq)
+    ks = np.array([classes[i][0] for i in cls], np.int32)
+    efs = np.array([classes[i][1] for i in cls], np.int32)
+    k_max, ef_max = int(ks.max()), int(efs.max())
+    with torch.cuda.stream(stream):
+        kd, efd = torch.from_numpy(ks).to(dev), torch.from_numpy(efs).to(dev)
+        w, h, cw, _, beam = idx.autotune_mixed(Qs, kd, efd, k_max, ef_max)
+        ids, _, st = idx.search_mixed(Qs, kd, efd, k_max=k_max, ef_max=ef_max, stats=True)
+    stream.synchronize()
+    ids = ids.cpu().numpy()
+    per_class = []
+    for i, (k, ef) in enumerate(classes):
+        sel = np.nonzero(cls == i)[0]
+        per_class.append({"k": k, "ef": ef, "queries": int(sel.size),
+                          f"recall@{k}": round(synth.recall(ids[sel, :k], gt[sel, :k], k), 4) if sel.size else None})
+    mixed_ms, mixed_kms = timed(lambda: idx.search_mixed(Qs, kd, efd, k_max=k_max, ef_max=ef_max))
+    E = int(st[:, 0].sum().item())
+    # the same queries, one plain launch per class (each class's rows contiguous, its own tuned shape)
+    sep_ms = 0.0
+    for i, (k, ef) in enumerate(classes):
+        sel = torch.from_numpy(np.nonzero(cls == i)[0]).to(dev)
+        if sel.numel() == 0:
+            continue
+        with torch.cuda.stream(stream):
+            Qc = Qs.index_select(0, sel).contiguous()
+            idx.autotune(Qc, k, ef)
+        stream.synchronize()
+        ms, _ = timed(lambda: idx.search(Qc, k, ef))
+        sep_ms += ms
+    mixed = {"classes": per_class, "launch": [w, h, cw, beam], "qps": round(nq / mixed_ms * 1e3, 1),
+             "ms_per_call": round(mixed_ms, 4), "kernel_ms": round(mixed_kms, 4), "mean_expansions": round(E / nq, 2),
+             "kernel_gbps": round((E * idx.block_bytes + int((4 * D + 8 * ks).sum())) / (mixed_kms * 1e-3) / 1e9, 1),
+             "one_plain_launch_per_class_ms": round(sep_ms, 4),
+             "one_plain_launch_per_class_qps": round(nq / sep_ms * 1e3, 1)}
+    log(f"[gist] mixed {mixed}")
+    print(json.dumps({"leg": "GIST-shaped 1M x 960", "workload": f"1M x 960 fp32 rank-64 non-negative factor model "
+                      f"plus N(0, 0.05^2) noise, R={R}, {nq} queries; recall against brute-force top-100",
+                      **ginfo, "n_gpus": 1, "steps": args.steps, "block_bytes": idx.block_bytes,
+                      "fixed_k10": out["k10"], "fixed_k100": out["k100"], "mixed": mixed,
+                      "hbm_peak_gbps": HBM_PEAK / 1e9, "cpu_baseline": None}), flush=True)
+    idx.free()
+
+
 def ls_study(args, dev):
     """Learned stop against fixed ef: for each recall@10 target, the smallest fixed beam that reaches it, and the
     fastest learned-stop setting whose recall on the test queries reaches it.  Workloads: the SIFT-shaped
@@ -706,7 +839,7 @@ def ls_study(args, dev):
         return learned_stop.recall_rows(ids, gth).mean().item()
 
     t_min, rows = 8, []
-    for target in (0.90, 0.95, 0.99):
+    for target in (float(x) for x in args.ls_targets.split(",")):
         margin = min(0.005, 0.2 * (1.0 - target))
         # the fixed beam picked like the stop's settings: on the held-out queries, with the same margin
         ho = None
@@ -738,7 +871,10 @@ def ls_study(args, dev):
                     break
         fx = fixed(hi)
         best = None
-        for ls_ef in dict.fromkeys((hi, next((x for x in EFS if x > hi), hi))):
+        # the stop's beams: the test-tuned and the held-out-picked fixed beams and the grid
+        # size above the larger (a stop needs a beam whose full search reaches the target)
+        top = max(hi, ho or hi)
+        for ls_ef in dict.fromkeys((hi, ho or hi, next((x for x in EFS if x > top), top))):
             # the stop kernels use 8 wavefronts per workgroup and no residency cap; the hash
             # factor is the one the autotuner picked for the fixed beam of the same size
             shape = fixed(ls_ef)["launch"]

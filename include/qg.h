@@ -81,8 +81,10 @@ int qg_build_index(const float *vectors, int64_t n, int32_t d, const int32_t *gr
 /* Flags of qg_build_graph. */
 enum {
   QG_GRAPH_REFINE = 1, /* supplement edges to exactly r per vertex (Sec. 3.2.2), random fill when too few */
-  QG_GRAPH_REPAIR = 2  /* link vertices unreachable from the entry (an addition: clustered data can leave the
-                          graph disconnected) */
+  QG_GRAPH_REPAIR = 2,  /* link vertices unreachable from the entry (an addition: clustered data can leave the
+                           graph disconnected) */
+  QG_GRAPH_PROGRESS = 4 /* print one line to stderr as each stage ends (iteration search and pruning,
+                           refinement, repair rounds), for builds that run for minutes */
 };
 
 /* Algorithm 2 (Indexing, Sec. 3.2) on `device`: starting from init_graph[n][r]
@@ -228,6 +230,16 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
 int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                 int32_t *out_wpb, int32_t *out_hash_factor, int32_t *out_cu_waves, int32_t *out_beam,
                 double *out_ms);
+
+/* qg_autotune for mixed batches: times qg_search_mixed on the given device
+ * queries and per-query k and ef (device int32[nq] each, bounded by k_max and
+ * ef_max as in qg_search_mixed) over the same settings, and keeps the fastest
+ * for later searches of this index (plain and mixed alike).  Errors and
+ * outputs as qg_autotune's.  (Runtime plumbing with no counterpart in the
+ * paper.) */
+int qg_autotune_mixed(qg_index *idx, const float *queries, int64_t nq, const int32_t *k_per_query,
+                      const int32_t *ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags, int32_t *out_wpb,
+                      int32_t *out_hash_factor, int32_t *out_cu_waves, int32_t *out_beam, double *out_ms);
 
 /* Set the launch shape directly (as qg_autotune would): wavefronts per
  * workgroup (1, 2, 4 or 8), visited-hash factor F (2, 3 or 4), the cap on

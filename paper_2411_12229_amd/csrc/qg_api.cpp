@@ -615,11 +615,14 @@ int qg_search_mixed_stop(const qg_index* idx, const float* queries, int64_t nq, 
                      out_stats);
 }
 
-int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
-                int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam,
-                double* out_ms) {
-  if (!idx) return fail(QG_EINVAL, "index is NULL");
-  if (nq <= 0 || !queries) return fail(QG_EINVAL, "autotuning needs queries");
+// The autotuner over one kind of call: `call(ids, dists)` runs the search
+// being tuned into outputs of nq x kcap; `mixed` selects the mixed-batch
+// kernel's beam-storage rule (ef_bound is the largest beam of the batch;
+// kernel modes as in search_impl: 0 plain, 3 mixed batch).
+extern "C++" template <class Call>
+static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bound, bool mixed, Call call,
+                         int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam,
+                         double* out_ms) {
   DeviceGuard g(idx->device);
   int32_t* ids = nullptr;
   float* dists = nullptr;
@@ -635,8 +638,8 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
     (void)hipFree(ids);
     (void)hipFree(dists);
   };
-  if (hipMalloc(&ids, sizeof(int32_t) * (size_t)(nq * k)) != hipSuccess ||
-      hipMalloc(&dists, sizeof(float) * (size_t)(nq * k)) != hipSuccess ||
+  if (hipMalloc(&ids, sizeof(int32_t) * (size_t)(nq * kcap)) != hipSuccess ||
+      hipMalloc(&dists, sizeof(float) * (size_t)(nq * kcap)) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     cleanup();
     return fail(QG_ENOMEM, "autotune buffers");
@@ -646,11 +649,11 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
   // their typical time, not by one lucky call)
   auto time_it = [&](double& t) {
     t = -1.0;
-    if ((rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr))) return;
+    if ((rc = call(ids, dists))) return;
     float ms[7];
     for (int rep = 0; rep < 7 && rc == QG_OK; ++rep) {
       if (hipEventRecord(e0, idx->stream) != hipSuccess) rc = fail(QG_EDEVICE, "hipEventRecord");
-      if (!rc) rc = qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr);
+      if (!rc) rc = call(ids, dists);
       if (!rc && (hipEventRecord(e1, idx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                   hipEventElapsedTime(&ms[rep], e0, e1) != hipSuccess))
         rc = fail(QG_EDEVICE, "timing events");
@@ -693,8 +696,8 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
       }
     }
   }
-  if (!rc && qgk::beam_regs(false, 0, ef, idx->N) > 0) {  // the beam in LDS for the best shape
-    idx->cu_waves = best_cw;
+  if (!rc && qgk::beam_regs(false, mixed ? 3 : 0, ef_bound, idx->N) > 0) {
+    idx->cu_waves = best_cw;  // the beam in LDS for the best shape
     idx->beam_regs = false;
     double t;
     time_it(t);
@@ -715,6 +718,31 @@ int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int3
   if (out_beam) *out_beam = best_beam ? 1 : 0;
   if (out_ms) *out_ms = best;
   return QG_OK;
+}
+
+int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
+                int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam,
+                double* out_ms) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (nq <= 0 || !queries) return fail(QG_EINVAL, "autotuning needs queries");
+  if (k < 1 || k > QG_MAX_K) return fail(QG_EINVAL, "k out of range");
+  auto call = [&](int32_t* ids, float* dists) {
+    return qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr);
+  };
+  return autotune_impl(idx, nq, k, ef, false, call, out_wpb, out_hash_factor, out_cu_waves, out_beam, out_ms);
+}
+
+int qg_autotune_mixed(qg_index* idx, const float* queries, int64_t nq, const int32_t* k_per_query,
+                      const int32_t* ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags, int32_t* out_wpb,
+                      int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam, double* out_ms) {
+  if (!idx) return fail(QG_EINVAL, "index is NULL");
+  if (nq <= 0 || !queries || !k_per_query || !ef_per_query) return fail(QG_EINVAL, "autotuning needs queries");
+  if (k_max < 1 || k_max > QG_MAX_K) return fail(QG_EINVAL, "k_max out of range");
+  auto call = [&](int32_t* ids, float* dists) {
+    return qg_search_mixed(idx, queries, nq, k_per_query, ef_per_query, k_max, ef_max, flags, ids, dists, nullptr);
+  };
+  return autotune_impl(idx, nq, k_max, ef_max, true, call, out_wpb, out_hash_factor, out_cu_waves, out_beam,
+                       out_ms);
 }
 
 int qg_set_launch(qg_index* idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam) {

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -83,7 +84,8 @@ extern "C" int qg_build_graph(const float* vectors, int64_t n, int32_t d, int32_
   if (d <= 0 || d % 8 || r <= 0 || r > 64) return qgi::set_error(QG_EINVAL, "bad d or r");
   if (ef_build < 1 || ef_build > QG_MAX_K || iters < 0) return qgi::set_error(QG_EINVAL, "bad ef_build or iters");
   if (entry < 0 || entry >= n) return qgi::set_error(QG_EINVAL, "entry out of range");
-  if (flags & ~(QG_GRAPH_REFINE | QG_GRAPH_REPAIR)) return qgi::set_error(QG_EINVAL, "unknown flags");
+  if (flags & ~(QG_GRAPH_REFINE | QG_GRAPH_REPAIR | QG_GRAPH_PROGRESS))
+    return qgi::set_error(QG_EINVAL, "unknown flags");
   const bool refine = (flags & QG_GRAPH_REFINE) && iters > 0;
   if (refine && !fill) return qgi::set_error(QG_EINVAL, "refinement needs the fill ids");
   int ndev = 0;
@@ -91,6 +93,12 @@ extern "C" int qg_build_graph(const float* vectors, int64_t n, int32_t d, int32_
   if (device < 0 || device >= ndev) return qgi::set_error(QG_EINVAL, "bad device");
   DeviceScope scope(device);
   const auto t0 = std::chrono::steady_clock::now();
+  auto note = [&](const char* what, int i, int64_t count) {
+    if (!(flags & QG_GRAPH_PROGRESS)) return;
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[qg_build_graph] %.1fs %s %d: %lld\n", s, what, i, (long long)count);
+    std::fflush(stderr);
+  };
   const int C = ef_build + r;  // candidate capacity: EF results and R old neighbours
   const int64_t chunk = std::min<int64_t>(n, 65536);
   DevBuf G, cid, cd, ncand, kidx, nkept, sids, sdist;
@@ -123,15 +131,21 @@ extern "C" int qg_build_graph(const float* vectors, int64_t n, int32_t d, int32_
     qg_free_index(idx);
     if (rc) return rc;
     HIP_OR_FAIL(es, "search for candidates");
+    note("iteration, vertices searched", it, n);
     HIP_OR_FAIL(qgg::launch_nsg(vectors, d, r, n, C, cid.as<int32_t>(), cd.as<double>(), ncand.as<int32_t>(),
                                 G.as<int32_t>(), kidx.as<int32_t>(), nkept.as<int32_t>(), nullptr),
                 "NSG pruning");
+    if (flags & QG_GRAPH_PROGRESS) {
+      HIP_OR_FAIL(hipDeviceSynchronize(), "NSG pruning");
+      note("iteration, lists pruned", it, n);
+    }
   }
   if (refine)
     HIP_OR_FAIL(qgg::launch_refine(vectors, d, r, n, C, 1, cid.as<int32_t>(), ncand.as<int32_t>(),
                                    kidx.as<int32_t>(), nkept.as<int32_t>(), fill, G.as<int32_t>(), nullptr),
                 "refinement");
   HIP_OR_FAIL(hipDeviceSynchronize(), "graph construction");
+  if (refine) note("refinement done", iters - 1, n);
 
   int64_t stats[4] = {0, 0, 0, 0};
   if (flags & QG_GRAPH_REPAIR) {
@@ -153,8 +167,11 @@ extern "C" int qg_build_graph(const float* vectors, int64_t n, int32_t d, int32_
     DevBuf unr_d, qv_d, ws_d, rowd_d;
     int64_t cap = 0, wcap = 0;
     stats[0] = reach_from(H, n, r, entry, seen, queue);
+    note("repair, reachable before", 0, stats[0]);
     for (int round = 0; round < 64; ++round) {
-      if (reach_from(H, n, r, entry, seen, queue) == n) break;
+      const int64_t reached = reach_from(H, n, r, entry, seen, queue);
+      if (round) note("repair round, reachable", round, reached);
+      if (reached == n) break;
       unr.clear();
       for (int64_t v = 0; v < n; ++v)
         if (!seen[(size_t)v]) unr.push_back((int32_t)v);

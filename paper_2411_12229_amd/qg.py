@@ -22,6 +22,7 @@ QG_SEARCH_SMALL_HASH = 2
 QG_SEARCH_LDS_BEAM = 4
 QG_GRAPH_REFINE = 1
 QG_GRAPH_REPAIR = 2
+QG_GRAPH_PROGRESS = 4
 QG_NOALLOC_SCRATCH_BYTES = 16 << 20
 QG_MAX_EF = 2048
 QG_MAX_K = 1024
@@ -70,6 +71,8 @@ def _load():
         "qg_set_launch": ([P, i32, i32, i32, i32], c_int),
         "qg_autotune": ([P, P, i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                          ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
+        "qg_autotune_mixed": ([P, P, i64, P, P, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                               ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
         "qg_index_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)], c_int),
         "qg_timing": ([P, c_int], c_int),
@@ -147,6 +150,19 @@ class Index:
         w, h, c, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _check(_lib.qg_autotune(self._h, _dev(queries, torch.float32, "queries"), queries.shape[0], k, ef, flags,
                                 ctypes.byref(w), ctypes.byref(h), ctypes.byref(c), ctypes.byref(b), ctypes.byref(ms)))
+        return w.value, h.value, c.value, ms.value, b.value
+
+    def autotune_mixed(self, queries: torch.Tensor, k: torch.Tensor, ef: torch.Tensor, k_max: int, ef_max: int,
+                       flags: int = 0):
+        """autotune for mixed batches (per-query k and ef, int32 device tensors [nq]); same return values."""
+        nq = queries.shape[0]
+        if k.shape != (nq,) or ef.shape != (nq,):
+            raise ValueError("shape mismatch")
+        w, h, c, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.qg_autotune_mixed(self._h, _dev(queries, torch.float32, "queries"), nq,
+                                      _dev(k, torch.int32, "k_per_query"), _dev(ef, torch.int32, "ef_per_query"),
+                                      int(k_max), int(ef_max), flags, ctypes.byref(w), ctypes.byref(h),
+                                      ctypes.byref(c), ctypes.byref(b), ctypes.byref(ms)))
         return w.value, h.value, c.value, ms.value, b.value
 
     def set_launch(self, wpb: int, hash_factor: int, cu_waves: int = 0, beam: int = 1) -> None:
@@ -277,12 +293,14 @@ def qg_load_index(path: str, device: int = 0) -> Index:
 
 
 def qg_build_graph(vectors: torch.Tensor, r: int, ef_build: int, iters: int, rotation: torch.Tensor, entry: int,
-                   init_graph: torch.Tensor, fill: torch.Tensor | None, refine: bool = True, repair: bool = True):
+                   init_graph: torch.Tensor, fill: torch.Tensor | None, refine: bool = True, repair: bool = True,
+                   progress: bool = False):
     """Algorithm 2 on the vectors' device -> (graph int32 [n, r] on the device, stats dict)."""
     n, d = vectors.shape
     out = torch.empty((n, r), dtype=torch.int32, device=vectors.device)
     st = (ctypes.c_int64 * 4)()
-    flags = (QG_GRAPH_REFINE if refine else 0) | (QG_GRAPH_REPAIR if repair else 0)
+    flags = (QG_GRAPH_REFINE if refine else 0) | (QG_GRAPH_REPAIR if repair else 0) | \
+        (QG_GRAPH_PROGRESS if progress else 0)
     _check(_lib.qg_build_graph(_dev(vectors, torch.float32, "vectors"), n, d, r, ef_build, iters,
                                _dev(rotation, torch.float32, "rotation"), int(entry),
                                _dev(init_graph, torch.int32, "init_graph"),

@@ -41,7 +41,8 @@ CONFIGS = {
     2: Config(2, 1_000_000, 128, 32, 10_000, 10, (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512),
               "SIFT-shaped: 1000-cluster mixture, integer values clipped to [0,255]"),
     3: Config(3, 1_000_000, 960, 64, 1_000, 10, (64, 128, 256), "GIST-shaped: rank-64 non-negative factor model"),
-    4: Config(4, 1_000_000, 768, 32, 10_000, 10, (64, 128, 256), "unit-norm rank-128 plus noise, shifted queries"),
+    4: Config(4, 1_000_000, 768, 32, 10_000, 10, (64, 128, 256),
+              "unit-norm rank-128 (1000 overlapping blobs in a 16-d latent) plus noise, shifted queries"),
     5: Config(5, 5_000_000, 96, 32, 10_000, 10, (32, 64, 128), "unit-norm 4096-cluster mixture"),
 }
 
@@ -119,14 +120,40 @@ def gen_data(cfg: int, n: int | None = None, nq: int | None = None, D: int | Non
 
         return draw(g, n), draw(gq, nq)
     if cfg == 4:
-        U = (g.standard_normal((D, 128)) / math.sqrt(D)).astype(f32)
-        gvec = g.standard_normal(128)  # the query shift is part of the distribution, not of one query draw
-        shift = (0.5 * math.sqrt(128) * gvec / np.linalg.norm(gvec)).astype(f32)
-        X = chunked(n, lambda b: _normalize(g.standard_normal((b, 128), dtype=f32) @ U.T
-                                            + f32(0.06) * g.standard_normal((b, D), dtype=f32)))
-        Q = chunked(nq, lambda b: _normalize((gq.standard_normal((b, 128), dtype=f32) + shift) @ U.T
-                                             + f32(0.06) * gq.standard_normal((b, D), dtype=f32)))
-        return X, Q
+        # Unit-norm rank-128 data plus noise: a 128-d latent z mapped to 768-d
+        # by one random U, plus N(0, 0.06^2) per coordinate, renormalised.  The
+        # latent is shaped like the SIFT-shaped set's: 1000 overlapping blobs in
+        # a shared 16-d space (centres N(0, I), within-blob N(0, I)) mapped by a
+        # random W, 8 blob-specific directions (total variance 0.28^2 per latent
+        # coordinate) and an N(0, 0.1^2) floor, so the local dimension is about
+        # 15 while the span is all 128 dims.  Queries come from the same
+        # distribution with the latent mean moved by half its RMS norm along a
+        # random direction.
+        L, dl, dc, nb = 128, 16, 8, 1000
+        U = (g.standard_normal((D, L)) / math.sqrt(D)).astype(f32)
+        W = (g.standard_normal((L, dl)) / math.sqrt(dl)).astype(f32)
+        zc = g.standard_normal((nb, dl)).astype(f32)
+        Ac = (g.standard_normal((nb, L, dc)) * (0.28 / math.sqrt(dc))).astype(f32)
+        gvec = g.standard_normal(L)  # the query shift is part of the distribution, not of one query draw
+        rms = math.sqrt(L * (2.0 + 0.28 ** 2 + 0.1 ** 2))
+        shift = (0.5 * rms * gvec / np.linalg.norm(gvec)).astype(f32)
+
+        def draw(gg, m, sh):
+            lab = gg.integers(0, nb, m)
+            pos = [0]
+
+            def row(b):
+                s = pos[0]
+                pos[0] += b
+                li = lab[s:s + b]
+                z = (zc[li] + gg.standard_normal((b, dl), dtype=f32)) @ W.T
+                z += np.einsum("blc,bc->bl", Ac[li], gg.standard_normal((b, dc), dtype=f32))
+                z += f32(0.1) * gg.standard_normal((b, L), dtype=f32) + sh
+                return _normalize(z @ U.T + f32(0.06) * gg.standard_normal((b, D), dtype=f32))
+
+            return chunked(m, row)
+
+        return draw(g, n, f32(0.0)), draw(gq, nq, shift)
     if cfg == 5:
         mu = _normalize(g.standard_normal((4096, D)))
         X = chunked(n, lambda b: _normalize(mu[g.integers(0, 4096, b)]

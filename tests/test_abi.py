@@ -45,6 +45,8 @@ def test_error_paths_without_device():
                                     None) == -1
     assert lib.qg_server_set_stop(None, None) == -1
     assert lib.qg_autotune(None, None, ctypes.c_int64(0), 10, 10, 0, None, None, None, None, None) == -1
+    assert lib.qg_autotune_mixed(None, None, ctypes.c_int64(0), None, None, 10, 10, 0, None, None, None, None,
+                                 None) == -1
     srv = ctypes.c_void_p(1)
     assert lib.qg_server_create(None, 2, 64, 10, 64, ctypes.byref(srv)) == -1 and srv.value is None
     assert lib.qg_server_submit(None, None, 1, 1, ctypes.c_uint64(0)) == -1
@@ -75,8 +77,11 @@ def test_load_refuses_repeated_neighbour_ids(tmp_path):
     G = synth.knn_graph(X, 32, 4)
     G[17, 9] = G[17, 3] = -1
     oracle.write_index(path, oracle.encode(X, G, M), 128, 32, e, M)
-    lib.qg_load_index(path.encode(), 0, ctypes.byref(out))
-    assert b"repeats" not in (lib.qg_last_error() or b"")
+    rc = lib.qg_load_index(path.encode(), 0, ctypes.byref(out))
+    # loads on a device; without one it fails for that reason, not for the format
+    assert rc == 0 or (rc != -4 and b"repeats" not in (lib.qg_last_error() or b""))
+    if rc == 0:
+        lib.qg_free_index(out)
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path):

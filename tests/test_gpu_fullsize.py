@@ -55,7 +55,8 @@ def oracle_blocks_for(X, G, M, verts):
     return blocks
 
 
-def check_full_size(cfg, X, Q, G, M, k, ef, launch, n_blocks=256, n_queries=48, seed=0, no_me_ef=0):
+def check_full_size(cfg, X, Q, G, M, k, ef, launch, n_blocks=256, n_queries=48, seed=0, no_me_ef=0,
+                    mixed_classes=()):
     N, D = X.shape
     R = G.shape[1]
     e = synth.medoid(X)
@@ -87,19 +88,45 @@ def check_full_size(cfg, X, Q, G, M, k, ef, launch, n_blocks=256, n_queries=48, 
         assert np.array_equal(dists[qs], od), "w/o ME: distances differ"
         assert np.array_equal(st[qs, :3], os_[:, :3]), "w/o ME: counters differ"
         say(f"  w/o ME ef={no_me_ef}: {n_queries} sampled queries equal")
+    if mixed_classes:  # one mixed launch, every query its own (k, ef), in the shape the mixed-batch tuner picks
+        cls = rng.integers(0, len(mixed_classes), len(Q))
+        ks = np.array([mixed_classes[i][0] for i in cls], np.int32)
+        efs = np.array([mixed_classes[i][1] for i in cls], np.int32)
+        k_max, ef_max = int(ks.max()), int(efs.max())
+        Qd, kd, efd = T(Q), T(ks), T(efs)
+        tuned = idx.autotune_mixed(Qd, kd, efd, k_max, ef_max)
+        ids, dists, st = idx.search_mixed(Qd, kd, efd, k_max=k_max, ef_max=ef_max, stats=True)
+        torch.cuda.synchronize()
+        ids, dists, st = ids.cpu().numpy(), dists.cpu().numpy(), st.cpu().numpy()
+        for i, (kc, efc) in enumerate(mixed_classes):
+            sel = qs[cls[qs] == i]
+            if sel.size == 0:
+                continue
+            oi, od, os_ = oracle.search(dev_blocks, D, R, e, M, Q[sel], kc, efc, with_stats=True)
+            assert np.array_equal(ids[sel, :kc], oi), f"mixed class (k={kc}, ef={efc}): ids differ"
+            assert np.array_equal(dists[sel, :kc], od), f"mixed class (k={kc}, ef={efc}): distances differ"
+            assert np.array_equal(st[sel, :3], os_[:, :3]), f"mixed class (k={kc}, ef={efc}): counters differ"
+            assert (ids[sel, kc:] == -1).all() and np.isinf(dists[sel, kc:]).all()
+        say(f"  mixed launch {mixed_classes} in shape {tuned[:3] + tuned[4:]}: sampled rows equal")
 
 
 def test_sift_shaped_full_size():
-    """1M x 128, R = 32, the benchmark's input graph, 10,000 queries at the
-    benchmark's beam (68) in a launch shape its autotuner picks, and at the
-    default shape;
-    the w/o ME search at the beam that reaches the same recall (48)."""
+    """1M x 128, R = 32, the benchmark's graph (Algorithm 2 on the device,
+    EF = 400, t = 3, from the same seeds), 10,000 queries at the benchmark's
+    beam (48) in the launch shape its autotuner picked (8 wavefronts per
+    workgroup, F = 3, no cap, beam in registers), at the default shape with
+    the beam in LDS, and the w/o ME search at ef 32."""
     c = synth.SIFT_LIKE
     X, Q = synth.gen_data(c)
     M = synth.rotation(128, synth.seed(c, "rotation"))
-    G = synth.knn_graph(X, 32, synth.seed(c, "long"), device=DEV)
-    check_full_size(c, X, Q, G, M, 10, 68, (2, 4, 24))
-    check_full_size(c, X, Q, G, M, 10, 68, (4, 3, 0), seed=1, no_me_ef=48)
+    e = synth.medoid(X)
+    G0 = T(synth.random_graph(len(X), 32, synth.seed(c, "graph")))
+    fill = T(synth.random_graph(len(X), 32, synth.seed(c, "fill")))
+    Gd, st = qg.qg_build_graph(T(X), 32, 400, 3, T(M), e, G0, fill, progress=True)
+    G = Gd.cpu().numpy()
+    say(f"Algorithm 2 graph: {st}")
+    check_full_size(c, X, Q, G, M, 10, 48, (8, 3, 0, 1))
+    check_full_size(c, X, Q, G, M, 10, 48, (4, 3, 0, 0), seed=1, no_me_ef=32)
 
 
 def test_serving_shaped_full_size():
@@ -114,9 +141,11 @@ def test_serving_shaped_full_size():
 
 def test_gist_shaped_full_size():
     """1M x 960, R = 64 (12.3 GB of blocks), with a seeded random graph,
-    1,000 queries at k = 100."""
+    1,000 queries at k = 100, then one mixed launch of k = 10 and k = 100 at
+    two beams each (the 1M x 960 bench leg's kind of batch)."""
     c = synth.GIST_LIKE
     X, Q = synth.gen_data(c)
     M = synth.rotation(960, synth.seed(c, "rotation"))
     G = synth.random_graph(len(X), 64, synth.seed(c, "graph"))
-    check_full_size(c, X, Q, G, M, 100, 128, (4, 3, 0), n_blocks=64, n_queries=8)
+    check_full_size(c, X, Q, G, M, 100, 128, (4, 3, 0), n_blocks=64, n_queries=24,
+                    mixed_classes=((10, 48), (10, 128), (100, 160), (100, 256)))

@@ -223,3 +223,29 @@ def test_autotune_keeps_results(cfg1, k, ef):
         with pytest.raises(qg.QGError):
             idx.set_launch(*bad)
     idx.set_launch(wpb, hf, cw, beam)
+
+
+def test_autotune_mixed_keeps_results(cfg1):
+    """The mixed-batch tuner times the mixed kernel over the same settings and
+    only changes the launch shape: the batch's rows still equal the oracle's
+    per query, before and after."""
+    c = cfg1
+    rng = np.random.default_rng(11)
+    nq = 200
+    ks = rng.choice([1, 10, 100], nq).astype(np.int32)
+    efs = rng.choice([16, 48, 160], nq).astype(np.int32)
+    Qd, kd, efd = T(c["Q"][:nq]), T(ks), T(efs)
+    before = c["idx"].search_mixed(Qd, kd, efd, k_max=100, ef_max=160, stats=True)
+    wpb, hf, cw, ms, beam = c["idx"].autotune_mixed(Qd, kd, efd, 100, 160)
+    print(f"autotune mixed: wpb={wpb} hash factor={hf} cu waves={cw} beam={beam} {ms:.3f} ms", flush=True)
+    assert wpb in (1, 2, 4, 8) and hf in (2, 3, 4) and cw in (0, 16, 20, 24) and beam == 1 and ms > 0
+    after = c["idx"].search_mixed(Qd, kd, efd, k_max=100, ef_max=160, stats=True)
+    torch.cuda.synchronize()
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)
+    oi, od, ost = _oracle_rows(c, c["Q"][:nq], ks, efs, 100)
+    assert np.array_equal(after[0].cpu().numpy(), oi) and np.array_equal(after[1].cpu().numpy(), od)
+    assert np.array_equal(after[2].cpu().numpy(), ost)
+    with pytest.raises(qg.QGError):  # k_max above the largest result count
+        c["idx"].autotune_mixed(Qd, kd, efd, qg.QG_MAX_K + 1, 160)
+    c["idx"].set_launch(4, 3, 0, 1)
