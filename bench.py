@@ -709,22 +709,24 @@ def gist_leg(args, dev):
 
     out = {"k10": [], "k100": []}
     pick = {}
-    for k, grid in ((10, (16, 32, 48, 64, 96, 128, 192, 256)), (100, (100, 128, 160, 192, 256, 384, 512))):
-        for target in (0.95, 0.99):
+    targets = (0.90, 0.95)
+    for k, grid in ((10, (16, 32, 48, 64, 96, 128, 192, 256, 384, 512)),
+                    (100, (100, 128, 160, 192, 256, 384, 512, 768, 1024))):
+        for target in targets:
             pick.setdefault((k, target), None)
         for ef in grid:
             row, rec = fixed(k, ef)
             out[f"k{k}"].append(row)
-            for target in (0.95, 0.99):
+            for target in targets:
                 if pick[(k, target)] is None and rec >= target:
                     pick[(k, target)] = ef
-            if rec >= 0.99:
+            if rec >= targets[-1]:
                 break
-    # the mixed batch: each query draws one of four classes -- k = 10 or 100, at the beam that reaches
-    # recall 0.95 or 0.99 for that k (the largest grid beam where a target was not reached)
+    # the mixed batch: each query draws one of four classes -- k = 10 or 100, at the smallest grid beam
+    # that reaches recall 0.90 or 0.95 for that k (the largest grid beam where a target was not reached)
     classes = []
     for k in (10, 100):
-        for target in (0.95, 0.99):
+        for target in targets:
             ef = pick[(k, target)] or out[f"k{k}"][-1]["ef"]
             classes.append((k, ef))
     rng = np.random.default_rng(synth.seed(c, "queries"))
