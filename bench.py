@@ -74,6 +74,74 @@ def make_graph(c, X, M, entry, dev, kind, build_ef=400, build_iters=3):
     return G, info
 
 
+def serve_trace(qg, idx, Q, qsel, ks, efs, arrival, ef_max, stop=None, with_ids=False, streams=3,
+                max_batch=8192):
+    """Replay one open-loop trace through the library's serving loop.  Returns (row, tags, ids or None): the
+    row holds the completed rate, p50/p99 latency and where the slowest 1% of requests spent their time,
+    from the server's batch records (queue wait before their batch was taken, host enqueue, device time
+    between the batch's events, and the rest until the worker saw completion)."""
+    srv = qg.Server(idx, streams=streams, max_batch=max_batch, k_max=int(ks.max()), ef_max=ef_max)
+    try:
+        if stop is not None:
+            srv.set_stop(*stop)
+        # latencies are taken by the server when each batch completes; results are collected after the trace
+        t0 = time.perf_counter()
+        srv.replay(Q[qsel], ks, efs, arrival)
+        srv.drain()
+        wall = time.perf_counter() - t0
+        parts, got = [], 0
+        while got < len(qsel):
+            parts.append(srv.poll(1 << 18, payload=with_ids, with_batch=True))
+            got += len(parts[-1][0])
+        st = srv.stats()
+        rec = srv.batches()
+    finally:
+        srv.close()
+    tags = np.concatenate([p[0] for p in parts]).astype(np.int64)
+    ids = np.concatenate([p[1] for p in parts]) if with_ids else None
+    lat = np.concatenate([p[3] for p in parts])
+    bat = np.concatenate([p[4] for p in parts])
+    n = len(qsel)
+    p50, p99 = np.percentile(lat, [50, 99])
+    row = {"requests": n, "completed_per_s": round(n / wall, 1), "p50_ms": round(float(p50) * 1e3, 3),
+           "p99_ms": round(float(p99) * 1e3, 3), "batches": st["batches"], "mean_batch": round(n / max(st["batches"], 1), 1),
+           "largest_batch": st["largest_batch"], "tail": serving_tail(lat, bat, rec, efs[tags])}
+    return row, tags, ids
+
+
+def serving_tail(lat, bat, rec, ef_req):
+    """Where the slowest 1% of requests spent their time, from the batch records: median of each part for the
+    tail and for all requests, and the batches that hold most of the tail."""
+    b = bat
+    t_sub = rec["t_done"][b] - lat
+    parts = {"queue_wait": rec["t_dispatch"][b] - t_sub, "host_enqueue": rec["t_enqueued"][b] - rec["t_dispatch"][b],
+             "device": rec["device_ms"][b].astype(np.float64) / 1e3}
+    parts["after_device"] = lat - parts["queue_wait"] - parts["host_enqueue"] - parts["device"]
+    tail = lat >= np.percentile(lat, 99)
+    med = lambda sel: {k: round(float(np.median(v[sel])) * 1e3, 3) for k, v in parts.items()}
+    tb, cnt = np.unique(b[tail], return_counts=True)
+    order = np.argsort(-cnt)[:4]
+    first_dispatch = rec["t_dispatch"].min() if len(rec) else 0.0
+    worst = []
+    for i, c in zip(tb[order], cnt[order]):
+        r = rec[i]
+        worst.append({"batch": int(i), "tail_requests": int(c), "n": int(r["n"]), "ef_max": int(r["ef_max"]),
+                      "k_max": int(r["k_max"]), "slot": int(r["slot"]),
+                      "at_ms": round((r["t_dispatch"] - first_dispatch) * 1e3, 2),
+                      "oldest_wait_ms": round((r["t_dispatch"] - r["t_oldest"]) * 1e3, 3),
+                      "host_enqueue_ms": round((r["t_enqueued"] - r["t_dispatch"]) * 1e3, 3),
+                      "device_ms": round(float(r["device_ms"]), 3),
+                      "after_device_ms": round((r["t_done"] - r["t_enqueued"]) * 1e3 - float(r["device_ms"]), 3),
+                      # the slots busy when this batch was taken, and the beams they ran
+                      "busy_slots_at_dispatch": [[int(x["slot"]), int(x["ef_max"]), int(x["n"])] for x in
+                                                 rec[(rec["t_dispatch"] < r["t_dispatch"]) &
+                                                     (r["t_dispatch"] < rec["t_done"])][:8]]})
+    cls, cnt_cls = np.unique(ef_req[tail], return_counts=True)
+    return {"tail_requests": int(tail.sum()), "tail_by_ef": {int(a): int(c) for a, c in zip(cls, cnt_cls)},
+            "tail_median_ms": med(tail), "all_median_ms": med(np.ones_like(tail)), "tail_batches": int(len(tb)),
+            "worst_batches": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,9 +179,9 @@ def main():
     ap.add_argument("--ls-study", action="store_true",
                     help="instead of the benchmark line: learned stop against fixed ef at recall@10 0.90 / 0.95 / "
                          "0.99 (one JSON line)")
-    ap.add_argument("--workload", default="sift", choices=("sift", "gist960"),
+    ap.add_argument("--workload", default="sift", choices=("sift", "gist960", "serve5m"),
                     help="gist960: the 1M x 960 leg (R=64, k=10 and k=100, uneven beams in one mixed launch); "
-                         "prints its own JSON line")
+                         "serve5m: the serving loop on 5M x 96 with target recalls; each prints its own JSON line")
     ap.add_argument("--ls-targets", default="0.90,0.95,0.99", help="recall@10 targets of --ls-study")
     ap.add_argument("--ls-workload", default="sift", choices=("sift", "unit768"),
                     help="workload of --ls-study: the SIFT-shaped benchmark set or 1M x 768 unit-norm")
@@ -135,6 +203,8 @@ def main():
         return ls_study(args, dev)
     if args.workload == "gist960":
         return gist_leg(args, dev)
+    if args.workload == "serve5m":
+        return serve_leg(args, dev)
     cfg = synth.CONFIGS[synth.SIFT_LIKE]
     D, R, k = cfg.D, cfg.R, cfg.k
     if args.load_index:
@@ -520,31 +590,9 @@ def main():
             ks = rng.choice([1, 10, 100], n).astype(np.int32)
             efs = rng.choice(ef_classes, n).astype(np.int32)
             arrival = np.cumsum(rng.exponential(1.0 / rate, n))
-            srv = qg.Server(idx, streams=3, max_batch=8192, k_max=100, ef_max=max(ef_classes))
-            try:
-                if with_stop:
-                    srv.set_stop(bits, ls_res["theta"], t_min=ls_res["t_min"], t_every=ls_res["t_every"])
-                # latencies are taken by the server when each batch completes; results are
-                # collected after the trace (a Python loop polling during the trace stalled
-                # the server threads once for ~5 ms per run, a harness effect)
-                t0 = time.perf_counter()
-                srv.replay(Q[qsel], ks, efs, arrival)
-                srv.drain()
-                wall = time.perf_counter() - t0
-                got, lat = 0, []
-                while got < n:
-                    t, _, _, l = srv.poll(1 << 18, payload=False)
-                    got += len(t)
-                    lat.append(l)
-                st = srv.stats()
-            finally:
-                srv.close()
-            lat = np.concatenate(lat)
-            p50, p99 = np.percentile(lat, [50, 99])
-            row = {"offered_per_s": rate, "learned_stop": with_stop, "requests": n,
-                   "completed_per_s": round(n / wall, 1),
-                   "p50_ms": round(p50 * 1e3, 3), "p99_ms": round(p99 * 1e3, 3), "batches": st["batches"],
-                   "mean_batch": round(n / max(st["batches"], 1), 1), "largest_batch": st["largest_batch"]}
+            stop = (bits, ls_res["theta"], ls_res["t_min"], ls_res["t_every"]) if with_stop else None
+            res, _, _ = serve_trace(qg, idx, Q, qsel, ks, efs, arrival, max(ef_classes), stop=stop)
+            row = {"offered_per_s": rate, "learned_stop": with_stop, **res}
             serving.append(row)
             log(f"[bench] serving {rate:,}/s offered: {row}")
 
@@ -770,6 +818,115 @@ def gist_leg(args, dev):
                       **ginfo, "n_gpus": 1, "steps": args.steps, "block_bytes": idx.block_bytes,
                       "fixed_k10": out["k10"], "fixed_k100": out["k100"], "mixed": mixed,
                       "hbm_peak_gbps": HBM_PEAK / 1e9, "cpu_baseline": None}), flush=True)
+    idx.free()
+
+
+def serve_leg(args, dev):
+    """The serving loop on the Deep-like 5M x 96 set (unit-norm 4096-cluster mixture, R = 32, Algorithm 2 graph):
+    open-loop Poisson arrivals at 50k-500k requests/s, each request with k ~ U{1, 10, 100} and a target recall
+    ~ U{0.90, 0.95, 0.99}.  The target maps to a beam per (k, target), calibrated on 4,000 held-out queries
+    (the smallest grid beam whose recall@k there reaches the target plus a margin); served results are scored
+    against brute force per class.  One more trace runs every batch with the learned stop, whose model is
+    trained on traces of held-out queries and whose theta is the most eager one that keeps every class at its
+    target on the held-out queries."""
+    import torch
+
+    import synth
+    from paper_2411_12229_amd import learned_stop, qg
+
+    c = synth.DEEP_LIKE
+    cfg = synth.CONFIGS[c]
+    D, R = cfg.D, cfg.R
+    t0 = time.time()
+    X, Q = synth.gen_data(c)
+    _, Qh = synth.gen_data(c, n=1, nq=8_000, qseed=synth.seed(c, "train"))
+    M = synth.rotation(D, synth.seed(c, "rotation"))
+    entry = synth.medoid(X)
+    log(f"[serve] data {X.shape}, {len(Q)} test and {len(Qh)} held-out queries in {time.time() - t0:.1f}s")
+    G, ginfo = make_graph(c, X, M, entry, dev, args.graph, args.build_ef, args.build_iters)
+    idx = qg.qg_build_index(torch.from_numpy(X).to(dev), torch.from_numpy(G).to(dev), torch.from_numpy(M).to(dev),
+                            entry)
+    del G
+    gt, _ = synth.ground_truth(X, Q, 100, device=dev)
+    gth, _ = synth.ground_truth(X, Qh, 100, device=dev)
+    del X
+    log(f"[serve] index and ground truth ready at {time.time() - t0:.1f}s")
+    Qhd, gthd = torch.from_numpy(Qh).to(dev), torch.from_numpy(gth).to(dev)
+    Qcal, gcal = Qhd[:4_000].contiguous(), gthd[:4_000]   # beam and theta calibration
+    Qtr, gtr = Qhd[4_000:].contiguous(), gthd[4_000:]     # learned-stop training traces
+    ks_all, targets = (1, 10, 100), (0.90, 0.95, 0.99)
+    grid = (4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 160, 192, 256, 384, 512, 768, 1024, 1536, 2048)
+
+    def cal_recall(k, ef):
+        ids, _ = idx.search(Qcal, k, ef)
+        return learned_stop.recall_rows(ids, gcal[:, :k]).mean().item()
+
+    ef_map = {}
+    for k in ks_all:
+        for target in targets:
+            margin = min(0.005, 0.2 * (1.0 - target))
+            ef_map[(k, target)] = next((e for e in grid if e >= min(k, 16) and cal_recall(k, e) >= target + margin),
+                                       grid[-1])
+    log(f"[serve] beam per (k, target recall): {ef_map}")
+    ef_max = max(ef_map.values())
+
+    # the learned stop: trained on k = 10 traces at the 0.95 beam; theta = the smallest on a grid for which
+    # every (k, target) class keeps its target (plus margin) on the calibration queries with its own beam
+    t_min, t_every = 8, 8
+    ef_tr = ef_map[(10, 0.95)]
+    feat, lab = learned_stop.collect(idx, Qtr, gtr[:, :10], 10, ef_tr, t_min, 4)
+    bits = learned_stop.export(learned_stop.train(feat, lab, epochs=6))
+    theta = None
+    for th in np.arange(-2.0, 16.01, 0.5):
+        ok = True
+        for (k, target), e in ef_map.items():
+            ids, _, _, _ = idx.search_stop(Qcal, k, e, bits, theta=float(th), t_min=t_min, t_every=t_every)
+            if learned_stop.recall_rows(ids, gcal[:, :k]).mean().item() < target + min(0.005, 0.2 * (1 - target)):
+                ok = False
+                break
+        if ok:
+            theta = float(th)
+            break
+    log(f"[serve] learned stop: trained on {feat.shape[0]} trace points at ef {ef_tr}; theta {theta}")
+
+    idx.set_launch(4, 3, 0, 1)
+    rng = np.random.default_rng(synth.seed(c, "queries") + 100)
+    rows = []
+    legs = [(r, False) for r in (50_000, 100_000, 200_000, 350_000, 500_000)]
+    if theta is not None:
+        legs.append((200_000, True))
+    for rate, with_stop in legs:
+        n = int(rate * 1.0)
+        qsel = rng.integers(0, len(Q), n)
+        ks = rng.choice(ks_all, n).astype(np.int32)
+        tg = rng.integers(0, len(targets), n)
+        efs = np.array([ef_map[(int(k), targets[t])] for k, t in zip(ks, tg)], np.int32)
+        arrival = np.cumsum(rng.exponential(1.0 / rate, n))
+        stop = (bits, theta, t_min, t_every) if with_stop else None
+        res, tags, ids = serve_trace(qg, idx, Q, qsel, ks, efs, arrival, ef_max, stop=stop, with_ids=True)
+        per_class = []
+        for k in ks_all:
+            for ti, target in enumerate(targets):
+                rows_c = np.nonzero((ks[tags] == k) & (tg[tags] == ti))[0]
+                if rows_c.size == 0:
+                    continue
+                got = ids[rows_c, :k]
+                want = gt[qsel[tags[rows_c]], :k]
+                rec = float(np.mean([len(set(a.tolist()) & set(b.tolist())) / k for a, b in zip(got, want)]))
+                per_class.append({"k": k, "target": target, "ef": ef_map[(k, target)], "requests": int(rows_c.size),
+                                  "recall": round(rec, 4)})
+        row = {"offered_per_s": rate, "learned_stop": with_stop, **res, "recall_by_class": per_class}
+        rows.append(row)
+        log(f"[serve] {rate:,}/s offered{' (learned stop)' if with_stop else ''}: "
+            f"{ {k: row[k] for k in ('completed_per_s', 'p50_ms', 'p99_ms', 'mean_batch')} }")
+    print(json.dumps({"leg": "serving loop, Deep-like 5M x 96",
+                      "workload": f"5M x 96 unit-norm 4096-cluster mixture, R={R}, {len(Q)} test queries drawn with "
+                                  "replacement; open-loop Poisson arrivals; k ~ U{1,10,100}, target recall ~ "
+                                  "U{0.90,0.95,0.99} mapped to a beam on 4,000 held-out queries; 3 streams, batches "
+                                  "up to 8192", **ginfo, "n_gpus": 1, "beam_per_k_and_target":
+                      {f"k{k}@{t}": e for (k, t), e in ef_map.items()},
+                      "learned_stop": {"trained_at_ef": ef_tr, "trace_points": int(feat.shape[0]), "theta": theta,
+                                       "t_min": t_min, "t_every": t_every}, "rates": rows}), flush=True)
     idx.free()
 
 

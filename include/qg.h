@@ -261,8 +261,10 @@ int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_wa
  * in a batch for long ones, and the slots overlap transfers with searches.  Every request's results are those of qg_search_ex
  * for that query alone with its own k and ef.  The index must outlive the
  * server; 1 <= streams <= 16, 1 <= k_max <= QG_MAX_K, 1 <= ef_max <= QG_MAX_EF.
- * Creation runs one single-query search on every slot (synchronously) so
- * that the kernels are loaded before the first request. */
+ * Creation runs single-query searches on every slot (synchronously), one
+ * for each beam storage a batch can use, so that every kernel a batch may
+ * launch is loaded before the first request; qg_server_set_stop does the same
+ * for the stop kernels. */
 typedef struct qg_server qg_server;
 
 int qg_server_create(qg_index *idx, int32_t streams, int32_t max_batch, int32_t k_max, int32_t ef_max,
@@ -285,9 +287,32 @@ int qg_server_submit(qg_server *s, const float *query, int32_t k, int32_t ef, ui
  * Host outputs, each nullable: tags[n], ids[n][k_max] and dists[n][k_max]
  * (a request's k results, then (-1, +inf)), latency_s[n] (submission, or
  * for a replayed request its scheduled arrival, to completion seen by the
- * worker, seconds).  Returns the number written, or a negative QG_* code. */
+ * worker, seconds), batch[n] (the index of the request's batch record, see
+ * qg_server_batches; -1 past the records kept).  Returns the number written,
+ * or a negative QG_* code. */
 int64_t qg_server_poll(qg_server *s, int64_t max_results, uint64_t *tags, int32_t *ids, float *dists,
-                       double *latency_s);
+                       double *latency_s, int64_t *batch);
+
+/* One batch the serving loop ran.  Host times are seconds on the clock the
+ * latencies use (steady, arbitrary origin). */
+typedef struct {
+  double t_oldest;   /* arrival (submission or scheduled arrival) of its oldest request */
+  double t_dispatch; /* the worker took the batch from the queue */
+  double t_enqueued; /* its uploads, search, downloads and event were enqueued */
+  double t_done;     /* the worker saw the batch's event complete (0 while in flight) */
+  float device_ms;   /* device time between an event before the uploads and one after the downloads
+                        (-1 while in flight) */
+  int32_t n;         /* requests in the batch */
+  int32_t ef_max;    /* largest beam among them (the launch is sized for it) */
+  int32_t k_max;     /* largest k among them */
+  int32_t slot;      /* the stream slot it ran on */
+} qg_server_batch;
+
+/* Copy batch records [first, first + max) (host out[max]); the server keeps
+ * the first 2^22.  Returns the number copied, or a negative QG_* code.
+ * (Instrumentation of the serving loop: a slow request is traced through its
+ * batch index from qg_server_poll to where its time went.) */
+int64_t qg_server_batches(qg_server *s, int64_t first, int64_t max, qg_server_batch *out);
 
 /* Submit queries[n][d] (host) with tags 0 .. n-1 at arrival_s[i] seconds after
  * the call (an open-loop arrival trace; arrival_s non-decreasing), from a

@@ -12,7 +12,9 @@
 // batch of short searches never waits for a long one and is sized for its own
 // beam (more wavefronts fit), and the S slots overlap transfers with searches.
 // Latency is measured on the host from submission to the moment the worker
-// sees the batch's event complete.
+// sees the batch's event complete.  Every batch leaves a record (host times of
+// its oldest arrival, dispatch, enqueue and completion, and its device time
+// between two events), so that a slow request can be traced to what held it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +48,7 @@ struct Request {
 
 // One finished batch: its rows are handed out by poll, oldest first.
 struct DoneBatch {
+  int64_t seq = 0;           // index of the batch's record
   std::vector<uint64_t> tags;
   std::vector<int32_t> ks;
   std::vector<double> latency;
@@ -58,7 +61,8 @@ struct DoneBatch {
 struct Slot {
   qg_index* view = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t start = nullptr;  // before the uploads (timing)
+  hipEvent_t done = nullptr;   // after the downloads (timing)
   float* h_q = nullptr;  // pinned host staging
   int32_t* h_k = nullptr;
   int32_t* h_ef = nullptr;
@@ -70,6 +74,7 @@ struct Slot {
   int32_t* d_ids = nullptr;
   float* d_dists = nullptr;
   std::vector<Request> batch;
+  int64_t seq = -1;  // record of the batch in flight
   bool busy = false;
 };
 
@@ -91,6 +96,8 @@ struct qg_server {
   bool use_stop = false;         // batches run with the learned stop (qg_server_set_stop)
   qg_stop_params stop_params{};
   int64_t submitted = 0, completed = 0, batches = 0, largest = 0;
+  static constexpr size_t kMaxRecords = size_t(1) << 22;  // batch records kept (the first 4M)
+  std::vector<qg_server_batch> records;
   int error = QG_OK;
   std::string errmsg;
   bool stop = false;
@@ -112,15 +119,46 @@ void free_slot(Slot& s) {
   (void)hipHostFree(s.h_ids);
   (void)hipHostFree(s.h_dists);
   if (s.done) (void)hipEventDestroy(s.done);
+  if (s.start) (void)hipEventDestroy(s.start);
   if (s.view) qg_free_index(s.view);
   if (s.stream) (void)hipStreamDestroy(s.stream);
   s = Slot{};
 }
 
+// One batch of a single zero query through every step a batch takes
+// (uploads, search, downloads, events) for each beam storage a batch can get
+// (a beam of one entry, of 65 and of 129: one or two register words per lane,
+// or LDS), with the stop if `stop` is given, so that every kernel a batch may
+// launch is loaded, and the copy paths set up, before the first request: the
+// first launch of a kernel loads its code and takes milliseconds.
+bool warm_up(qg_server* sv, Slot& s, const qg_stop_params* stop) {
+  const size_t K = (size_t)sv->k_max, D = (size_t)sv->D;
+  std::memset(s.h_q, 0, sizeof(float) * D);
+  s.h_k[0] = 1;
+  for (int32_t ef : {1, 65, 129}) {
+    if (ef > sv->ef_max) break;
+    s.h_ef[0] = ef;
+    const bool ok =
+        hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * D, hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+        hipMemcpyAsync(s.d_k, s.h_k, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+        hipMemcpyAsync(s.d_ef, s.h_ef, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
+        (stop ? qg_search_mixed_stop(s.view, s.d_q, 1, s.d_k, s.d_ef, sv->k_max, ef, 0, stop, s.d_ids, s.d_dists,
+                                     nullptr)
+              : qg_search_mixed(s.view, s.d_q, 1, s.d_k, s.d_ef, sv->k_max, ef, 0, s.d_ids, s.d_dists, nullptr)) ==
+            QG_OK &&
+        hipMemcpyAsync(s.h_ids, s.d_ids, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
+        hipMemcpyAsync(s.h_dists, s.d_dists, sizeof(float) * K, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
+        hipEventRecord(s.done, s.stream) == hipSuccess && hipEventSynchronize(s.done) == hipSuccess &&
+        hipEventQuery(s.done) == hipSuccess;
+    if (!ok) return false;
+  }
+  return true;
+}
+
 bool init_slot(qg_server* sv, Slot& s) {
   const size_t B = (size_t)sv->max_batch, K = (size_t)sv->k_max, D = (size_t)sv->D;
   if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return false;
-  if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return false;
+  if (hipEventCreate(&s.done) != hipSuccess || hipEventCreate(&s.start) != hipSuccess) return false;
   if (hipHostMalloc(&s.h_q, sizeof(float) * B * D) != hipSuccess ||
       hipHostMalloc(&s.h_k, sizeof(int32_t) * B) != hipSuccess ||
       hipHostMalloc(&s.h_ef, sizeof(int32_t) * B) != hipSuccess ||
@@ -135,20 +173,7 @@ bool init_slot(qg_server* sv, Slot& s) {
   s.view = qgi::make_view(sv->idx);
   if (!s.view) return false;
   if (qg_set_stream(s.view, s.stream) != QG_OK || qg_reserve(s.view, sv->max_batch) != QG_OK) return false;
-  // one batch of a single zero query (k = 1, ef = 1) through every step a
-  // batch takes (uploads, search, downloads, event), so that kernels and copy
-  // paths are set up before the first request arrives
-  std::memset(s.h_q, 0, sizeof(float) * D);
-  s.h_k[0] = 1;
-  s.h_ef[0] = 1;
-  return hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * D, hipMemcpyHostToDevice, s.stream) == hipSuccess &&
-         hipMemcpyAsync(s.d_k, s.h_k, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
-         hipMemcpyAsync(s.d_ef, s.h_ef, sizeof(int32_t), hipMemcpyHostToDevice, s.stream) == hipSuccess &&
-         qg_search_mixed(s.view, s.d_q, 1, s.d_k, s.d_ef, sv->k_max, 1, 0, s.d_ids, s.d_dists, nullptr) == QG_OK &&
-         hipMemcpyAsync(s.h_ids, s.d_ids, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
-         hipMemcpyAsync(s.h_dists, s.d_dists, sizeof(float) * K, hipMemcpyDeviceToHost, s.stream) == hipSuccess &&
-         hipEventRecord(s.done, s.stream) == hipSuccess && hipEventSynchronize(s.done) == hipSuccess &&
-         hipEventQuery(s.done) == hipSuccess;
+  return warm_up(sv, s, nullptr);
 }
 
 void fail_server(qg_server* sv, const std::string& msg) {
@@ -167,7 +192,9 @@ int ef_class(int32_t ef) {
 }
 
 // Enqueue one batch on a free slot.  Returns false on a device error.
-bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
+bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take, int slot) {
+  qg_server_batch rec{};
+  rec.t_dispatch = now_s();
   const int n = (int)take.size();
   const size_t D = (size_t)sv->D;
   for (int i = 0; i < n; ++i) {
@@ -176,14 +203,20 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
     s.h_ef[i] = take[i].ef;
   }
   const size_t K = (size_t)sv->k_max;
-  if (hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * D * n, hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+  if (hipEventRecord(s.start, s.stream) != hipSuccess ||
+      hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * D * n, hipMemcpyHostToDevice, s.stream) != hipSuccess ||
       hipMemcpyAsync(s.d_k, s.h_k, sizeof(int32_t) * n, hipMemcpyHostToDevice, s.stream) != hipSuccess ||
       hipMemcpyAsync(s.d_ef, s.h_ef, sizeof(int32_t) * n, hipMemcpyHostToDevice, s.stream) != hipSuccess) {
     fail_server(sv, "upload of a batch failed");
     return false;
   }
-  int32_t ef_batch = 1;
-  for (int i = 0; i < n; ++i) ef_batch = std::max(ef_batch, take[i].ef);
+  int32_t ef_batch = 1, k_batch = 1;
+  double oldest = take[0].t_submit;
+  for (int i = 0; i < n; ++i) {
+    ef_batch = std::max(ef_batch, take[i].ef);
+    k_batch = std::max(k_batch, take[i].k);
+    oldest = std::min(oldest, take[i].t_submit);
+  }
   const int rc = sv->use_stop ? qg_search_mixed_stop(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, ef_batch, 0,
                                                      &sv->stop_params, s.d_ids, s.d_dists, nullptr)
                               : qg_search_mixed(s.view, s.d_q, n, s.d_k, s.d_ef, sv->k_max, ef_batch, 0, s.d_ids,
@@ -197,6 +230,19 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take) {
       hipEventRecord(s.done, s.stream) != hipSuccess) {
     fail_server(sv, "download of a batch failed");
     return false;
+  }
+  rec.t_enqueued = now_s();
+  rec.t_oldest = oldest;
+  rec.n = n;
+  rec.ef_max = ef_batch;
+  rec.k_max = k_batch;
+  rec.slot = slot;
+  rec.device_ms = -1.0f;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    s.seq = (int64_t)sv->records.size();
+    if (sv->records.size() < qg_server::kMaxRecords) sv->records.push_back(rec);
+    else s.seq = -1;
   }
   s.batch = std::move(take);
   s.busy = true;
@@ -222,6 +268,8 @@ void worker_loop(qg_server* sv) {
         continue;
       }
       const double t = now_s();
+      float dev_ms = -1.0f;
+      if (hipEventElapsedTime(&dev_ms, s.start, s.done) != hipSuccess) dev_ms = -1.0f;
       const size_t n = s.batch.size();
       DoneBatch db;  // built outside the lock: one record per batch, reusing a polled one's storage
       {
@@ -232,6 +280,7 @@ void worker_loop(qg_server* sv) {
         }
       }
       db.next = db.pos = 0;
+      db.seq = s.seq;
       db.tags.resize(n);
       db.ks.resize(n);
       db.latency.resize(n);
@@ -250,13 +299,18 @@ void worker_loop(qg_server* sv) {
       progressed = true;
       {
         std::lock_guard<std::mutex> lk(sv->mu);
+        if (s.seq >= 0) {
+          sv->records[(size_t)s.seq].t_done = t;
+          sv->records[(size_t)s.seq].device_ms = dev_ms;
+        }
         sv->done.push_back(std::move(db));
         sv->completed += (int64_t)n;
       }
       sv->cv_done.notify_all();
     }
     // dispatch whatever waits onto a free slot
-    for (auto& s : sv->slots) {
+    for (size_t si = 0; si < sv->slots.size(); ++si) {
+      Slot& s = sv->slots[si];
       if (s.busy) continue;
       std::vector<Request> take;
       {
@@ -281,7 +335,7 @@ void worker_loop(qg_server* sv) {
         }
       }
       if (take.empty()) break;
-      if (!dispatch(sv, s, std::move(take))) break;
+      if (!dispatch(sv, s, std::move(take), (int)si)) break;
       any_busy = progressed = true;
     }
     std::unique_lock<std::mutex> lk(sv->mu);
@@ -347,6 +401,16 @@ int qg_server_set_stop(qg_server* sv, const qg_stop_params* stop) {
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->npending > 0 || sv->completed < sv->submitted)
     return qgi::set_error(QG_EINVAL, "requests are waiting or in flight");
+  if (stop) {
+    // the worker is idle (nothing waits or runs) and dispatches only under
+    // this lock, so slot 0 is free: load the stop kernels there first
+    int old = 0;
+    (void)hipGetDevice(&old);
+    (void)hipSetDevice(sv->device);
+    const bool ok = warm_up(sv, sv->slots[0], stop);
+    (void)hipSetDevice(old);
+    if (!ok) return qgi::set_error(QG_EDEVICE, "warm-up of the stop kernels failed");
+  }
   sv->use_stop = stop != nullptr;
   if (stop) sv->stop_params = *stop;
   return QG_OK;
@@ -375,7 +439,7 @@ int qg_server_submit(qg_server* sv, const float* query, int32_t k, int32_t ef, u
 }
 
 int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32_t* ids, float* dists,
-                       double* latency_s) {
+                       double* latency_s, int64_t* batch) {
   if (!sv || max_results < 0) return qgi::set_error(QG_EINVAL, "server is NULL or max_results < 0");
   // Finished batches are moved out under the lock and copied into the
   // caller's arrays after it is released: first writes to fresh caller memory
@@ -397,6 +461,7 @@ int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32
       const size_t r = b.next++;
       if (tags) tags[n] = b.tags[r];
       if (latency_s) latency_s[n] = b.latency[r];
+      if (batch) batch[n] = b.seq;
       const size_t k = (size_t)b.ks[r];
       for (size_t j = 0; j < K; ++j) {
         const bool in = j < k;
@@ -489,6 +554,15 @@ int qg_server_stats(qg_server* sv, int64_t* submitted, int64_t* completed, int64
   if (batches) *batches = sv->batches;
   if (largest_batch) *largest_batch = sv->largest;
   return QG_OK;
+}
+
+int64_t qg_server_batches(qg_server* sv, int64_t first, int64_t max, qg_server_batch* out) {
+  if (!sv || first < 0 || max < 0 || (max > 0 && !out)) return qgi::set_error(QG_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  const int64_t have = (int64_t)sv->records.size();
+  const int64_t n = std::max<int64_t>(0, std::min(max, have - first));
+  if (n > 0) std::memcpy(out, sv->records.data() + first, sizeof(qg_server_batch) * (size_t)n);
+  return n;
 }
 
 void qg_server_destroy(qg_server* sv) {

@@ -80,7 +80,8 @@ def _load():
         "qg_free_index": ([P], None),
         "qg_server_create": ([P, i32, i32, i32, i32, PP], c_int),
         "qg_server_submit": ([P, P, i32, i32, ctypes.c_uint64], c_int),
-        "qg_server_poll": ([P, i64, P, P, P, P], i64),
+        "qg_server_poll": ([P, i64, P, P, P, P, P], i64),
+        "qg_server_batches": ([P, i64, i64, P], i64),
         "qg_server_replay": ([P, P, P, P, P, i64], c_int),
         "qg_server_set_stop": ([P, ctypes.POINTER(StopParams)], c_int),
         "qg_server_drain": ([P, ctypes.c_double], c_int),
@@ -467,19 +468,36 @@ class Server:
             raise ValueError("query has the wrong dimension")
         _check(_lib.qg_server_submit(self._h, ctypes.c_void_p(q.ctypes.data), k, ef, ctypes.c_uint64(tag)))
 
-    def poll(self, max_results: int = 1 << 16, payload: bool = True):
-        """-> (tags uint64 [n], ids int32 [n,k_max], dists f32 [n,k_max], latency s [n]) of finished requests."""
+    def poll(self, max_results: int = 1 << 16, payload: bool = True, with_batch: bool = False):
+        """-> (tags uint64 [n], ids int32 [n,k_max], dists f32 [n,k_max], latency s [n][, batch index int64 [n]])
+        of finished requests."""
         tags = np.empty(max_results, np.uint64)
         lat = np.empty(max_results, np.float64)
+        bat = np.empty(max_results, np.int64) if with_batch else None
         ids = np.empty((max_results, self.k_max), np.int32) if payload else None
         dists = np.empty((max_results, self.k_max), np.float32) if payload else None
         n = _lib.qg_server_poll(self._h, max_results, ctypes.c_void_p(tags.ctypes.data),
                                 ctypes.c_void_p(ids.ctypes.data) if payload else None,
                                 ctypes.c_void_p(dists.ctypes.data) if payload else None,
-                                ctypes.c_void_p(lat.ctypes.data))
+                                ctypes.c_void_p(lat.ctypes.data),
+                                ctypes.c_void_p(bat.ctypes.data) if with_batch else None)
         if n < 0:
             _check(int(n))
-        return tags[:n], (ids[:n] if payload else None), (dists[:n] if payload else None), lat[:n]
+        out = (tags[:n], (ids[:n] if payload else None), (dists[:n] if payload else None), lat[:n])
+        return out + (bat[:n],) if with_batch else out
+
+    BATCH_RECORD = np.dtype([("t_oldest", np.float64), ("t_dispatch", np.float64), ("t_enqueued", np.float64),
+                             ("t_done", np.float64), ("device_ms", np.float32), ("n", np.int32),
+                             ("ef_max", np.int32), ("k_max", np.int32), ("slot", np.int32)],
+                            align=True)  # the C struct's layout: 56 bytes, padded to its doubles' alignment
+
+    def batches(self, first: int = 0, max_records: int = 1 << 22) -> np.ndarray:
+        """Batch records (a structured array, fields as qg_server_batch) from index `first`."""
+        out = np.zeros(max_records, self.BATCH_RECORD)
+        n = _lib.qg_server_batches(self._h, int(first), int(max_records), ctypes.c_void_p(out.ctypes.data))
+        if n < 0:
+            _check(int(n))
+        return out[:n]
 
     def replay(self, queries: np.ndarray, k: np.ndarray, ef: np.ndarray, arrival_s: np.ndarray) -> None:
         """Submit an open-loop trace (request i at arrival_s[i] seconds, tag i) from a library thread."""

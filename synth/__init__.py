@@ -43,7 +43,8 @@ CONFIGS = {
     3: Config(3, 1_000_000, 960, 64, 1_000, 10, (64, 128, 256), "GIST-shaped: rank-64 non-negative factor model"),
     4: Config(4, 1_000_000, 768, 32, 10_000, 10, (64, 128, 256),
               "unit-norm rank-128 (1000 overlapping blobs in a 16-d latent) plus noise, shifted queries"),
-    5: Config(5, 5_000_000, 96, 32, 10_000, 10, (32, 64, 128), "unit-norm 4096-cluster mixture"),
+    5: Config(5, 5_000_000, 96, 32, 10_000, 10, (32, 64, 128),
+              "unit-norm 4096-cluster mixture (overlapping blobs in a 16-d latent)"),
 }
 
 
@@ -155,12 +156,33 @@ def gen_data(cfg: int, n: int | None = None, nq: int | None = None, D: int | Non
 
         return draw(g, n, f32(0.0)), draw(gq, nq, shift)
     if cfg == 5:
-        mu = _normalize(g.standard_normal((4096, D)))
-        X = chunked(n, lambda b: _normalize(mu[g.integers(0, 4096, b)]
-                                            + f32(0.08) * g.standard_normal((b, D), dtype=f32)))
-        Q = chunked(nq, lambda b: _normalize(mu[gq.integers(0, 4096, b)]
-                                             + f32(0.08) * gq.standard_normal((b, D), dtype=f32)))
-        return X, Q
+        # Unit-norm 4096-blob mixture with a low local dimension (like the
+        # Deep embeddings it stands in for): blobs overlap in a shared 16-d
+        # latent space (centres N(0, I), within-blob N(0, I)) mapped to 96-d by
+        # a random W, plus 4 blob-specific directions (total variance 0.28^2
+        # per coordinate) and an N(0, 0.1^2) floor, renormalised.  Queries come
+        # from the same distribution.
+        dl, dc, nb = 16, 4, 4096
+        W = (g.standard_normal((D, dl)) / math.sqrt(dl)).astype(f32)
+        zc = g.standard_normal((nb, dl)).astype(f32)
+        Ac = (g.standard_normal((nb, D, dc)) * (0.28 / math.sqrt(dc))).astype(f32)
+
+        def draw(gg, m):
+            lab = gg.integers(0, nb, m)
+            pos = [0]
+
+            def row(b):
+                s = pos[0]
+                pos[0] += b
+                li = lab[s:s + b]
+                z = (zc[li] + gg.standard_normal((b, dl), dtype=f32)) @ W.T
+                z += np.einsum("bdc,bc->bd", Ac[li], gg.standard_normal((b, dc), dtype=f32))
+                z += f32(0.1) * gg.standard_normal((b, D), dtype=f32)
+                return _normalize(z)
+
+            return chunked(m, row)
+
+        return draw(g, n), draw(gq, nq)
     raise ValueError(cfg)
 
 
@@ -237,6 +259,9 @@ def _topk_rows_np(X: np.ndarray, Y: np.ndarray, k: int, exclude_self: bool = Fal
     return ids_out, d_out
 
 
+_TOPK_BLOCK = 1 << 20  # base rows per shortlist block of the torch brute force
+
+
 def _topk_rows_torch(X, Y, k: int, exclude_self: bool, device):
     """Same as _topk_rows_np on a torch device (fp32 GEMM shortlist, fp64 re-rank)."""
     import torch
@@ -252,11 +277,21 @@ def _topk_rows_torch(X, Y, k: int, exclude_self: bool, device):
         if s and (s // chunk) % 100 == 0:
             print(f"[synth] brute force {s}/{Y.shape[0]} rows, {time.time() - t0:.0f}s", file=sys.stderr, flush=True)
         y = torch.from_numpy(np.ascontiguousarray(Y[s:s + chunk])).to(device)
-        d = xx[None, :] - 2.0 * (y @ Xt.T)
-        if exclude_self:
-            r = torch.arange(y.shape[0], device=device)
-            d[r, s + r] = float("inf")
-        cand = torch.topk(d, kk, dim=1, largest=False, sorted=False).indices
+        # shortlist per block of at most 2^20 base rows, then over the blocks'
+        # shortlists (a top-k over a whole 5M-wide row is not relied on)
+        parts_v, parts_i = [], []
+        for b0 in range(0, N, _TOPK_BLOCK):
+            b1 = min(N, b0 + _TOPK_BLOCK)
+            d = xx[None, b0:b1] - 2.0 * (y @ Xt[b0:b1].T)
+            if exclude_self:
+                r = torch.arange(y.shape[0], device=device)
+                own = (s + r >= b0) & (s + r < b1)
+                d[r[own], (s + r[own] - b0)] = float("inf")
+            v, i = torch.topk(d, min(kk, b1 - b0), dim=1, largest=False, sorted=False)
+            parts_v.append(v)
+            parts_i.append(i + b0)
+        v, i = torch.cat(parts_v, 1), torch.cat(parts_i, 1)
+        cand = torch.gather(i, 1, torch.topk(v, kk, dim=1, largest=False, sorted=False).indices)
         exact = ((Xt[cand].double() - y.double()[:, None, :]) ** 2).sum(-1)
         if exclude_self:
             exact[cand == (s + torch.arange(y.shape[0], device=device))[:, None]] = float("inf")

@@ -100,10 +100,23 @@ def test_replay_open_loop_trace(cfg1):
     try:
         srv.replay(Q, ks, efs, arrival)
         srv.drain()
-        tags, ids, dists, lat = _collect(srv, n)
+        parts = []
+        while sum(len(p[0]) for p in parts) < n:
+            parts.append(srv.poll(with_batch=True))
+        tags, ids, dists, lat, bat = (np.concatenate([p[j] for p in parts]) for j in range(5))
         st = srv.stats()
+        rec = srv.batches()
     finally:
         srv.close()
+    # the batch records account for every request and batch, in time order
+    assert len(rec) == st["batches"] and rec["n"].sum() == n
+    assert (rec["t_oldest"] <= rec["t_dispatch"]).all() and (rec["t_dispatch"] <= rec["t_enqueued"]).all()
+    assert (rec["t_enqueued"] <= rec["t_done"]).all() and (rec["device_ms"] > 0).all()
+    assert set(rec["slot"].tolist()) <= {0, 1}
+    assert np.array_equal(np.bincount(bat, minlength=len(rec)), rec["n"])
+    assert (ks[tags] <= rec["k_max"][bat]).all() and (efs[tags] <= rec["ef_max"][bat]).all()
+    lat_from_rec = rec["t_done"][bat] - rec["t_oldest"][bat]  # the oldest request's latency bounds its batch's
+    assert (lat <= lat_from_rec + 1e-9).all()
     p50, p99 = np.percentile(lat, [50, 99])
     print(f"replay 50k/s: p50 {p50 * 1e6:.0f} us, p99 {p99 * 1e6:.0f} us, {st['batches']} batches", flush=True)
     assert sorted(tags.tolist()) == list(range(n))

@@ -513,3 +513,17 @@ def test_ls_trace_features_and_limits():
     assert (never[0] == plain[0]).all() and (never[2] == plain[2]).all()
     first = oracle.search_ls(blocks, 64, 16, e, M, Q, k, ef, w=w, theta=-np.inf, t_min=t_min, t_every=t_every)
     assert (first[2][:, 0] == np.minimum(t_min, plain[2][:, 0])).all()
+
+
+def test_brute_force_blocks_equal_one_pass(monkeypatch):
+    """The torch brute force (ground truth, k-NN graphs) shortlists per block
+    of base rows and then over the blocks; with blocks of 700 rows it returns
+    exactly what the numpy brute force returns, self-exclusion included."""
+    monkeypatch.setattr(synth, "_TOPK_BLOCK", 700)
+    X, Q = synth.gen_data(1, n=3000, nq=40)
+    a = synth._topk_rows_torch(X, Q, 10, False, "cpu")
+    b = synth._topk_rows_np(X, Q, 10)
+    assert np.array_equal(a[0], b[0]) and np.allclose(a[1], b[1], rtol=0, atol=1e-9)
+    a = synth._topk_rows_torch(X, X[:900], 10, True, "cpu")
+    b = synth._topk_rows_np(X, X[:900], 10, exclude_self=True)
+    assert np.array_equal(a[0], b[0])
