@@ -105,8 +105,33 @@ def serve_trace(qg, idx, Q, qsel, ks, efs, arrival, ef_max, stop=None, with_ids=
     p50, p99 = np.percentile(lat, [50, 99])
     row = {"requests": n, "completed_per_s": round(n / wall, 1), "p50_ms": round(float(p50) * 1e3, 3),
            "p99_ms": round(float(p99) * 1e3, 3), "batches": st["batches"], "mean_batch": round(n / max(st["batches"], 1), 1),
-           "largest_batch": st["largest_batch"], "tail": serving_tail(lat, bat, rec, efs[tags])}
+           "largest_batch": st["largest_batch"], "tail": serving_tail(lat, bat, rec, efs[tags]),
+           "worker": worker_gaps(rec, lat, bat, arrival[tags])}
     return row, tags, ids
+
+
+def worker_gaps(rec, lat, bat, arr):
+    """The serving worker's timeline from the batch records: the longest intervals in which it neither took
+    nor completed a batch, with the requests that arrived meanwhile (a worker that is not running shows up as
+    a long gap with arrivals), and the batch whose host enqueue took longest."""
+    if len(rec) == 0:
+        return None
+    t0 = float(np.median(rec["t_done"][bat] - lat - arr))  # trace start on the server's clock
+    ev = np.sort(np.concatenate([rec["t_dispatch"], rec["t_done"]]))
+    gaps = np.diff(ev)
+    out = []
+    for j in np.argsort(-gaps)[:3]:
+        a, b = ev[j], ev[j + 1]
+        waiting = int(np.count_nonzero((arr + t0 >= a) & (arr + t0 < b)))
+        busy = rec[(rec["t_dispatch"] <= a) & (rec["t_done"] >= b)]
+        out.append({"from_ms": round((a - t0) * 1e3, 2), "gap_ms": round((b - a) * 1e3, 3),
+                    "arrivals_in_gap": waiting, "batches_running_through_it": int(len(busy))})
+    enq = rec["t_enqueued"] - rec["t_dispatch"]
+    m = int(np.argmax(enq))
+    return {"longest_idle_gaps": out,
+            "slowest_enqueue": {"at_ms": round((rec["t_dispatch"][m] - t0) * 1e3, 2),
+                                "ms": round(float(enq[m]) * 1e3, 3), "n": int(rec["n"][m]),
+                                "ef_max": int(rec["ef_max"][m])}}
 
 
 def serving_tail(lat, bat, rec, ef_req):

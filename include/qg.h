@@ -213,7 +213,7 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
 /* Launch-shape autotuning.  Times qg_search_ex on the given device queries
  * (k, ef, flags as they will be used) for every combination of wavefronts per
  * workgroup (1, 2, 4, 8; halved at launch while the LDS does not fit) and
- * visited-hash size (2^h >= F * ef slots, F = 2, 3, 4; a smaller table leaves
+ * visited-hash size (2^h >= F * min(ef, 256) + max(ef - 256, 0) slots, F = 2, 3, 4; a smaller table leaves
  * room for more wavefronts, a larger one sends fewer queries to the overflow
  * pass), then, for the fastest pair, caps of 24, 20 and 16 resident
  * wavefronts per compute unit against no cap (a batch only a little larger

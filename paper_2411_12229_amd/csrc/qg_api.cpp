@@ -512,14 +512,18 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
 
   const int ef_cap = (ef + 3) / 4 * 4;
   const int k_cap = (k + 3) / 4 * 4;
-  // visited hash: 2^h >= 3 ef slots (at least 256), filled to at most one half;
-  // queries that visit more finish in the overflow pass
+  // visited hash: 2^h >= F ef slots (at least 256), filled to at most one half;
+  // queries that visit more finish in the overflow pass.  Past 256 entries the
+  // slots grow one per beam entry, not F: a search expands about 0.4-0.6 ef
+  // vertices at large beams (1M x 128: 238 at ef 512, 580 at ef 1536, at most
+  // 975), and a smaller table leaves LDS for more resident queries
   int hbits = 8;
   // w/o ME the set holds every estimated vertex, not only the visited ones: up
   // to R per expansion (measured: about two thirds of them new), for about ef
   // expansions
   const int64_t hash_want =
-      no_me ? (int64_t)idx->hash_factor * idx->R * (ef + 16) / 2 : (int64_t)idx->hash_factor * ef;
+      no_me ? (int64_t)idx->hash_factor * idx->R * (ef + 16) / 2
+            : (int64_t)idx->hash_factor * std::min(ef, 256) + std::max(ef - 256, 0);
   while ((1 << hbits) < hash_want && hbits < 14) ++hbits;
   if (flags & QG_SEARCH_SMALL_HASH) hbits = 7;
   qgk::SearchArgs a{};

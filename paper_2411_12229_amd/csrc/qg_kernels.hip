@@ -1122,34 +1122,49 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
         if (live0 && np0 < ef) beam[np0] = e0;
         if (live1 && np1 < ef) beam[np1] = e1;
       } else {
-        const int ci = lanes_below(V);
+        // Beams above 128 entries.  Each candidate finds lb (old entries <= it)
+        // by a binary search over the sorted beam; then the candidates are
+        // stored in rank order and each old entry finds cnt (candidates below
+        // it) by a binary search over them.  Old entries are moved top down, a
+        // chunk at a time; once a chunk lies wholly below the smallest
+        // candidate, it and every chunk under it stay where they are.
         for (int t = 0; t < nv4; t += 4) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) sidx += cbuf[t + u] < cand;
         }
         lbv = 0;
+        if (valid) {
+          int lo = 0, hi = size;  // beam[0, lo) <= cand < beam[hi, size)
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((beam[mid] & ~(uint64_t)kChecked) <= cand)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          lbv = lo;
+        }
+        wave_sync();  // every read of the unsorted candidates is done
+        if (valid) cbuf[sidx] = cand;
+        wave_sync();
+        const uint64_t cmin = cbuf[0];  // the same word for every lane
         for (int base = ((size - 1) >> 6) << 6; base >= 0; base -= 64) {  // top down
           const int i = base + lane;
           const bool live = i < size;
           const uint64_t e = live ? beam[i] : kNone;
           const uint64_t ke = e & ~(uint64_t)kChecked;
-          const uint64_t Lm = ballot(live);
-          int cnt = 0;
-          // four candidates per step, their words read together (the padding
-          // words compare below no entry and match no candidate's index)
-          for (int t = 0; t < nv4; t += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const bool lt = cbuf[t + u] < ke;
-              cnt += lt;
-              const int le = __popcll(Lm & ~ballot(lt));
-              lbv += (ci == t + u) ? le : 0;
-            }
+          const int top = size - 1 - base < 63 ? size - 1 - base : 63;
+          if (rdlane64(ke, top) < cmin) break;  // nothing here or below moves
+          int lo = 0, hi = nv;  // cbuf[0, lo) < ke <= cbuf[hi, nv)
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cbuf[mid] < ke)
+              lo = mid + 1;
+            else
+              hi = mid;
           }
-          const int np = i + cnt;
-          const uint64_t tm = ballot(live && np == ef - 1);
-          if (tm) tail = rdlane64(ke, first_lane(tm));
-          if (live && np < ef) beam[np] = e;
+          const int np = i + lo;
+          if (live && lo > 0 && np < ef) beam[np] = e;
         }
       }
       const int npos = sidx + lbv;
@@ -1159,6 +1174,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       wave_sync();
       const int first = (int)rdlane((uint32_t)npos, first_lane(ballot(valid && sidx == 0)));
       if (first < cursor) cursor = first;
+      if (size > 128 && size + nv >= ef) tail = beam[ef - 1] & ~(uint64_t)kChecked;  // the same word for every lane
       size = (size + nv < ef) ? size + nv : ef;
     }
 
