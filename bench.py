@@ -131,7 +131,14 @@ def worker_gaps(rec, lat, bat, arr):
     return {"longest_idle_gaps": out,
             "slowest_enqueue": {"at_ms": round((rec["t_dispatch"][m] - t0) * 1e3, 2),
                                 "ms": round(float(enq[m]) * 1e3, 3), "n": int(rec["n"][m]),
-                                "ef_max": int(rec["ef_max"][m])}}
+                                "ef_max": int(rec["ef_max"][m]),
+                                # CPU time the worker spent in it, and its context switches: a wall time far
+                                # above the CPU time with an involuntary switch means it was preempted
+                                "worker_cpu_ms": round(float(rec["enqueue_cpu_ms"][m]), 3),
+                                "voluntary_switches": int(rec["enqueue_nvcsw"][m]),
+                                "involuntary_switches": int(rec["enqueue_nivcsw"][m])},
+            "enqueues_over_1ms": int(np.count_nonzero(enq > 1e-3)),
+            "batches_preempted_in_enqueue": int(np.count_nonzero(rec["enqueue_nivcsw"] > 0))}
 
 
 def serving_tail(lat, bat, rec, ef_req):
@@ -207,6 +214,7 @@ def main():
     ap.add_argument("--workload", default="sift", choices=("sift", "gist960", "serve5m"),
                     help="gist960: the 1M x 960 leg (R=64, k=10 and k=100, uneven beams in one mixed launch); "
                          "serve5m: the serving loop on 5M x 96 with target recalls; each prints its own JSON line")
+    ap.add_argument("--serve-streams", type=int, default=3, help="stream slots of the serving loop")
     ap.add_argument("--ls-targets", default="0.90,0.95,0.99", help="recall@10 targets of --ls-study")
     ap.add_argument("--ls-workload", default="sift", choices=("sift", "unit768"),
                     help="workload of --ls-study: the SIFT-shaped benchmark set or 1M x 768 unit-norm")
@@ -616,7 +624,8 @@ def main():
             efs = rng.choice(ef_classes, n).astype(np.int32)
             arrival = np.cumsum(rng.exponential(1.0 / rate, n))
             stop = (bits, ls_res["theta"], ls_res["t_min"], ls_res["t_every"]) if with_stop else None
-            res, _, _ = serve_trace(qg, idx, Q, qsel, ks, efs, arrival, max(ef_classes), stop=stop)
+            res, _, _ = serve_trace(qg, idx, Q, qsel, ks, efs, arrival, max(ef_classes), stop=stop,
+                                    streams=args.serve_streams)
             row = {"offered_per_s": rate, "learned_stop": with_stop, **res}
             serving.append(row)
             log(f"[bench] serving {rate:,}/s offered: {row}")
@@ -928,7 +937,8 @@ def serve_leg(args, dev):
         efs = np.array([ef_map[(int(k), targets[t])] for k, t in zip(ks, tg)], np.int32)
         arrival = np.cumsum(rng.exponential(1.0 / rate, n))
         stop = (bits, theta, t_min, t_every) if with_stop else None
-        res, tags, ids = serve_trace(qg, idx, Q, qsel, ks, efs, arrival, ef_max, stop=stop, with_ids=True)
+        res, tags, ids = serve_trace(qg, idx, Q, qsel, ks, efs, arrival, ef_max, stop=stop, with_ids=True,
+                                     streams=args.serve_streams)
         per_class = []
         for k in ks_all:
             for ti, target in enumerate(targets):
@@ -947,8 +957,8 @@ def serve_leg(args, dev):
     print(json.dumps({"leg": "serving loop, Deep-like 5M x 96",
                       "workload": f"5M x 96 unit-norm 4096-cluster mixture, R={R}, {len(Q)} test queries drawn with "
                                   "replacement; open-loop Poisson arrivals; k ~ U{1,10,100}, target recall ~ "
-                                  "U{0.90,0.95,0.99} mapped to a beam on 4,000 held-out queries; 3 streams, batches "
-                                  "up to 8192", **ginfo, "n_gpus": 1, "beam_per_k_and_target":
+                                  f"U{{0.90,0.95,0.99}} mapped to a beam on 4,000 held-out queries; {args.serve_streams} "
+                                  "streams, batches up to 8192", **ginfo, "n_gpus": 1, "beam_per_k_and_target":
                       {f"k{k}@{t}": e for (k, t), e in ef_map.items()},
                       "learned_stop": {"trained_at_ef": ef_tr, "trace_points": int(feat.shape[0]), "theta": theta,
                                        "t_min": t_min, "t_every": t_every}, "rates": rows}), flush=True)

@@ -306,6 +306,9 @@ typedef struct {
   int32_t ef_max;    /* largest beam among them (the launch is sized for it) */
   int32_t k_max;     /* largest k among them */
   int32_t slot;      /* the stream slot it ran on */
+  float enqueue_cpu_ms;   /* CPU time the worker thread used between t_dispatch and t_enqueued */
+  int32_t enqueue_nvcsw;  /* the worker's voluntary context switches in that interval (it blocked) */
+  int32_t enqueue_nivcsw; /* its involuntary context switches in that interval (it was preempted) */
 } qg_server_batch;
 
 /* Copy batch records [first, first + max) (host out[max]); the server keeps

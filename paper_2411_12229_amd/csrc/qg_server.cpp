@@ -16,6 +16,8 @@
 // its oldest arrival, dispatch, enqueue and completion, and its device time
 // between two events), so that a slow request can be traced to what held it.
 #include <hip/hip_runtime.h>
+#include <sys/resource.h>
+#include <time.h>
 
 #include <algorithm>
 #include <atomic>
@@ -36,6 +38,23 @@ namespace {
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+// The calling thread's CPU time and context-switch counts.
+struct ThreadUsage {
+  double cpu_s = 0;
+  long nvcsw = 0, nivcsw = 0;
+  static ThreadUsage now() {
+    ThreadUsage u;
+    timespec ts{};
+    if (clock_gettime(CLOCK_THREAD_CPUTIME_ID, &ts) == 0) u.cpu_s = (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+    rusage ru{};
+    if (getrusage(RUSAGE_THREAD, &ru) == 0) {
+      u.nvcsw = ru.ru_nvcsw;
+      u.nivcsw = ru.ru_nivcsw;
+    }
+    return u;
+  }
+};
 
 struct Request {
   uint64_t tag = 0;
@@ -194,6 +213,7 @@ int ef_class(int32_t ef) {
 // Enqueue one batch on a free slot.  Returns false on a device error.
 bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take, int slot) {
   qg_server_batch rec{};
+  const ThreadUsage u0 = ThreadUsage::now();
   rec.t_dispatch = now_s();
   const int n = (int)take.size();
   const size_t D = (size_t)sv->D;
@@ -232,6 +252,10 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take, int slot) {
     return false;
   }
   rec.t_enqueued = now_s();
+  const ThreadUsage u1 = ThreadUsage::now();
+  rec.enqueue_cpu_ms = (float)((u1.cpu_s - u0.cpu_s) * 1e3);
+  rec.enqueue_nvcsw = (int32_t)(u1.nvcsw - u0.nvcsw);
+  rec.enqueue_nivcsw = (int32_t)(u1.nivcsw - u0.nivcsw);
   rec.t_oldest = oldest;
   rec.n = n;
   rec.ef_max = ef_batch;

@@ -488,8 +488,10 @@ class Server:
 
     BATCH_RECORD = np.dtype([("t_oldest", np.float64), ("t_dispatch", np.float64), ("t_enqueued", np.float64),
                              ("t_done", np.float64), ("device_ms", np.float32), ("n", np.int32),
-                             ("ef_max", np.int32), ("k_max", np.int32), ("slot", np.int32)],
-                            align=True)  # the C struct's layout: 56 bytes, padded to its doubles' alignment
+                             ("ef_max", np.int32), ("k_max", np.int32), ("slot", np.int32),
+                             ("enqueue_cpu_ms", np.float32), ("enqueue_nvcsw", np.int32),
+                             ("enqueue_nivcsw", np.int32)],
+                            align=True)  # the C struct's layout, padded to its doubles' alignment
 
     def batches(self, first: int = 0, max_records: int = 1 << 22) -> np.ndarray:
         """Batch records (a structured array, fields as qg_server_batch) from index `first`."""

@@ -3,6 +3,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "qg.h")
 LIB = os.path.join(ROOT, "paper_2411_12229_amd", "libqg.so")
@@ -98,3 +100,28 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "libqg.so is missing" in r.stderr
+
+
+def test_server_batch_record_layout_matches_header(tmp_path):
+    """The binding's view of qg_server_batch has the C struct's size and field
+    offsets (a program built from the header prints them)."""
+    import shutil
+    import subprocess
+
+    import numpy as np
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    from paper_2411_12229_amd import qg
+    dt = qg.Server.BATCH_RECORD
+    src = tmp_path / "layout.c"
+    fields = dt.names
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"qg.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(qg_server_batch));\n" +
+                   "".join(f"  printf(\"%zu\\n\", offsetof(qg_server_batch, {f}));\n" for f in fields) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[0] == dt.itemsize
+    assert out[1:] == [dt.fields[f][1] for f in fields]
+    assert np.zeros(1, dt).nbytes == out[0]
