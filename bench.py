@@ -194,8 +194,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch shape instead of the one qg_autotune picks for the benchmark queries")
     ap.add_argument("--launch", default="",
-                    help="wpb,hash_factor,cu_waves[,beam]: set this launch shape (beam 1: in registers where the "
-                         "beam size allows, the default; 0: in LDS) for every search instead of autotuning")
+                    help="wpb,hash_factor,cu_waves[,beam[,lut]]: set this launch shape (beam 1: in registers where "
+                         "the beam size allows, the default; 0: in LDS; lut 1: padded rows, the default; 0: packed) "
+                         "for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--ablation", action="store_true", help="also sweep the w/o ME ablation (Sec. 4.2.3)")
     ap.add_argument("--no-ablation", action="store_true", help=argparse.SUPPRESS)  # the ablation is opt-in
@@ -278,10 +279,10 @@ def main():
         Qs = Qd.clone()
     stream.synchronize()
 
-    shape = (4, 3, 0, 1)  # the library's default launch shape
+    shape = (4, 3, 0, 1, 1)  # the library's default launch shape
     if args.launch:
         shape = tuple(int(x) for x in args.launch.split(","))
-        shape = shape + (1,) * (4 - len(shape))
+        shape = shape + (1,) * (5 - len(shape))
         idx.set_launch(*shape)
 
     def run(ef, stats=False):
@@ -358,13 +359,13 @@ def main():
             idx.search(Qs, k, ef)
 
     tuned = {"waves_per_workgroup": shape[0], "hash_factor": shape[1], "resident_waves_per_cu_cap": shape[2],
-             "beam_in_registers": shape[3], "set_by": "--launch"} if args.launch else None
+             "beam_in_registers": shape[3], "lut_padded_rows": shape[4], "set_by": "--launch"} if args.launch else None
     if not args.no_autotune and not args.launch:
         with torch.cuda.stream(stream):
-            wpb_t, hf_t, cw_t, tms, beam_t = idx.autotune(Qs, k, ef)
-        shape = (wpb_t, hf_t, cw_t, beam_t)
+            wpb_t, hf_t, cw_t, tms, beam_t, lut_t = idx.autotune(Qs, k, ef)
+        shape = (wpb_t, hf_t, cw_t, beam_t, lut_t)
         tuned = {"waves_per_workgroup": wpb_t, "hash_factor": hf_t, "resident_waves_per_cu_cap": cw_t,
-                 "beam_in_registers": beam_t, "median_call_ms": round(tms, 4)}
+                 "beam_in_registers": beam_t, "lut_padded_rows": lut_t, "median_call_ms": round(tms, 4)}
         log(f"[bench] autotune: {tuned}")
     qps, ms_per_step, kern_ms, rot_ms = timed(plain)
     expansions = int(s[:, 0].sum())
@@ -409,7 +410,7 @@ def main():
         from paper_2411_12229_amd import learned_stop
         # the learned-stop searches, and both searches at 80,000 queries, run
         # without the residency cap (it was tuned for the plain search of this batch)
-        idx.set_launch(shape[0], shape[1], 0, shape[3])
+        idx.set_launch(shape[0], shape[1], 0, shape[3], shape[4])
         t0 = time.time()
         _, Qtr = synth.gen_data(synth.SIFT_LIKE, n=1, nq=20_000, qseed=synth.seed(synth.SIFT_LIKE, "train"))
         gt_tr, _ = synth.ground_truth(X, Qtr, k, device=dev)
@@ -583,7 +584,7 @@ def main():
     d_h = torch.empty((args.nq, k), dtype=torch.float32).pin_memory()
     use_ls = roofline["kernel"].endswith("learned stop")
     e2e_ef = ls_res["ef"] if use_ls else ef
-    idx.set_launch(shape[0], shape[1], 0 if use_ls else shape[2], shape[3])  # the shape the value was timed with
+    idx.set_launch(shape[0], shape[1], 0 if use_ls else shape[2], shape[3], shape[4])  # the shape the value was timed with
 
     def e2e():
         with torch.cuda.stream(stream):
@@ -611,7 +612,7 @@ def main():
     serving = None
     if not args.no_serve:
         serving = []
-        idx.set_launch(shape[0], shape[1], 0, shape[3])  # batches of every size: no residency cap
+        idx.set_launch(shape[0], shape[1], 0, shape[3], shape[4])  # batches of every size: no residency cap
         rng = np.random.default_rng(11)
         ef_classes = (max(ef // 2, 1), ef, 4 * ef)
         legs = [(r, False) for r in (50_000, 200_000, 1_000_000, 4_000_000)]
@@ -637,7 +638,7 @@ def main():
         idx_k = qg.qg_build_index(torch.from_numpy(X).to(dev), torch.from_numpy(Gk).to(dev),
                                   torch.from_numpy(M).to(dev), entry)
         idx_k.set_stream(stream)
-        idx_k.set_launch(shape[0], shape[1], shape[2], shape[3])
+        idx_k.set_launch(*shape)
         curve = []
         for e in (16, 24, 32, 48, 64, 68, 96, 128):
             with torch.cuda.stream(stream):
@@ -776,7 +777,7 @@ def gist_leg(args, dev):
 
     def fixed(k, ef):
         with torch.cuda.stream(stream):
-            w, h, cw, _, beam = idx.autotune(Qs, k, ef)
+            w, h, cw, _, beam, lut = idx.autotune(Qs, k, ef)
             ids, _, st = idx.search(Qs, k, ef, stats=True)
         stream.synchronize()
         rec = synth.recall(ids.cpu().numpy(), gt[:, :k], k)
@@ -785,7 +786,7 @@ def gist_leg(args, dev):
         row = {"k": k, "ef": ef, f"recall@{k}": round(rec, 4), "qps": round(nq / ms * 1e3, 1),
                "ms_per_call": round(ms, 4), "kernel_ms": round(kms, 4), "mean_expansions": round(E / nq, 2),
                "kernel_gbps": round((E * idx.block_bytes + nq * (4 * D + 8 * k)) / (kms * 1e-3) / 1e9, 1),
-               "launch": [w, h, cw, beam]}
+               "launch": [w, h, cw, beam, lut]}
         log(f"[gist] fixed {row}")
         return row, rec
 
@@ -818,7 +819,7 @@ def gist_leg(args, dev):
     k_max, ef_max = int(ks.max()), int(efs.max())
     with torch.cuda.stream(stream):
         kd, efd = torch.from_numpy(ks).to(dev), torch.from_numpy(efs).to(dev)
-        w, h, cw, _, beam = idx.autotune_mixed(Qs, kd, efd, k_max, ef_max)
+        w, h, cw, _, beam, lut = idx.autotune_mixed(Qs, kd, efd, k_max, ef_max)
         ids, _, st = idx.search_mixed(Qs, kd, efd, k_max=k_max, ef_max=ef_max, stats=True)
     stream.synchronize()
     ids = ids.cpu().numpy()
@@ -841,7 +842,7 @@ def gist_leg(args, dev):
         stream.synchronize()
         ms, _ = timed(lambda: idx.search(Qc, k, ef))
         sep_ms += ms
-    mixed = {"classes": per_class, "launch": [w, h, cw, beam], "qps": round(nq / mixed_ms * 1e3, 1),
+    mixed = {"classes": per_class, "launch": [w, h, cw, beam, lut], "qps": round(nq / mixed_ms * 1e3, 1),
              "ms_per_call": round(mixed_ms, 4), "kernel_ms": round(mixed_kms, 4), "mean_expansions": round(E / nq, 2),
              "kernel_gbps": round((E * idx.block_bytes + int((4 * D + 8 * ks).sum())) / (mixed_kms * 1e-3) / 1e9, 1),
              "one_plain_launch_per_class_ms": round(sep_ms, 4),
@@ -1017,7 +1018,7 @@ def ls_study(args, dev):
         if ef not in cache:
             with torch.cuda.stream(stream):
                 t = idx.autotune(Qs, k, ef)
-                shape = t[:3] + t[4:5]
+                shape = t[:3] + t[4:6]
                 ids, _, st = idx.search(Qs, k, ef, stats=True)
                 rec = synth.recall(ids.cpu().numpy(), gt, k)
                 q = rate(lambda: idx.search(Qs, k, ef))
@@ -1072,7 +1073,7 @@ def ls_study(args, dev):
             # the stop kernels use 8 wavefronts per workgroup and no residency cap; the hash
             # factor is the one the autotuner picked for the fixed beam of the same size
             shape = fixed(ls_ef)["launch"]
-            idx.set_launch(shape[0], shape[1], 0, shape[3])
+            idx.set_launch(shape[0], shape[1], 0, shape[3], shape[4])
             with torch.cuda.stream(stream):
                 feat, lab = learned_stop.collect(idx, Qtrain, gtrain, k, ls_ef, t_min, 4)
                 bits = learned_stop.export(learned_stop.train(feat, lab, epochs=6))

@@ -219,17 +219,20 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
  * wavefronts per compute unit against no cap (a batch only a little larger
  * than the resident query slots can finish sooner on fewer, less contended
  * slots), then, for beams of at most 128 entries, the beam kept in LDS
- * against the beam kept in registers.  The fastest setting is kept for later
- * searches of this index.  Each setting is timed as the median of seven calls
- * after one untimed call.  Results do not depend on the choice, only the
- * speed.  Outputs (host, nullable): the chosen wavefronts per workgroup, F,
- * the cap (0 = none), the beam storage (1 = registers where the beam size
- * allows, 0 = LDS) and the median time in ms of one qg_search_ex call in that
- * setting.
+ * against the beam kept in registers, then the LUT layout (the per-query
+ * table of Sec. 2.2's FastScan, int16 rows of 16 entries: a padding row
+ * between the lane groups that share a neighbour, so their lookups fall in
+ * different LDS banks, against packed rows).  The fastest setting is kept for
+ * later searches of this index.  Each setting is timed as the median of seven
+ * calls after one untimed call.  Results do not depend on the choice, only
+ * the speed.  Outputs (host, nullable): the chosen wavefronts per workgroup,
+ * F, the cap (0 = none), the beam storage (1 = registers where the beam size
+ * allows, 0 = LDS), the LUT layout (1 = padded rows, 0 = packed) and the
+ * median time in ms of one qg_search_ex call in that setting.
  * Synchronous; allocates and frees temporary outputs. */
 int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                 int32_t *out_wpb, int32_t *out_hash_factor, int32_t *out_cu_waves, int32_t *out_beam,
-                double *out_ms);
+                int32_t *out_lut, double *out_ms);
 
 /* qg_autotune for mixed batches: times qg_search_mixed on the given device
  * queries and per-query k and ef (device int32[nq] each, bounded by k_max and
@@ -239,15 +242,17 @@ int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int3
  * paper.) */
 int qg_autotune_mixed(qg_index *idx, const float *queries, int64_t nq, const int32_t *k_per_query,
                       const int32_t *ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags, int32_t *out_wpb,
-                      int32_t *out_hash_factor, int32_t *out_cu_waves, int32_t *out_beam, double *out_ms);
+                      int32_t *out_hash_factor, int32_t *out_cu_waves, int32_t *out_beam, int32_t *out_lut,
+                      double *out_ms);
 
 /* Set the launch shape directly (as qg_autotune would): wavefronts per
  * workgroup (1, 2, 4 or 8), visited-hash factor F (2, 3 or 4), the cap on
- * resident wavefronts per compute unit (0 = none, at most 64) and the beam
+ * resident wavefronts per compute unit (0 = none, at most 64), the beam
  * storage (1: in registers for beams of at most 128 entries, the default;
- * 0: always in LDS).  Results do not depend on it.  QG_EINVAL for values
- * outside these sets. */
-int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam);
+ * 0: always in LDS) and the LUT layout (1: padded rows, the default; 0:
+ * packed rows).  Results do not depend on it.  QG_EINVAL for values outside
+ * these sets. */
+int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam, int32_t lut);
 
 /* ---- Serving loop (continuous batching) ----------------------------------
  * A server owns `streams` slots over one index.  Each slot has its own

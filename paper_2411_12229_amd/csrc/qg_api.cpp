@@ -85,6 +85,7 @@ struct qg_index {
   int cu_waves = 0;  // cap on resident wavefronts per compute unit (0 = as many as fit)
   int cus = 256;     // compute units of the device (read at creation; sizes the persistent grid)
   bool beam_regs = true;  // beams of at most 128 entries live in registers (else in LDS)
+  bool lut_pad = true;    // LUT layout: a padding row between lane groups (else packed rows)
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev[2];  // pairs per kernel class
@@ -195,6 +196,7 @@ qg_index* make_view(const qg_index* base) {
   v->blocks = base->blocks;
   v->wpb_pref = base->wpb_pref;
   v->hash_factor = base->hash_factor;
+  v->lut_pad = base->lut_pad;
   v->cu_waves = base->cu_waves;
   v->cus = base->cus;
   v->beam_regs = base->beam_regs;
@@ -541,6 +543,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   a.k_cap = k_cap;
   a.ef_cap = ef_cap;
   a.hash_bits = hbits;
+  a.lut_pad = idx->lut_pad ? 1 : 0;
   a.flags = flags;
   a.entry = idx->entry;
   a.out_ids = out_ids;
@@ -626,15 +629,15 @@ int qg_search_mixed_stop(const qg_index* idx, const float* queries, int64_t nq, 
 extern "C++" template <class Call>
 static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bound, bool mixed, Call call,
                          int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam,
-                         double* out_ms) {
+                         int32_t* out_lut, double* out_ms) {
   DeviceGuard g(idx->device);
   int32_t* ids = nullptr;
   float* dists = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int keep_wpb = idx->wpb_pref, keep_hf = idx->hash_factor, keep_cw = idx->cu_waves;
-  const bool keep_beam = idx->beam_regs;
+  const bool keep_beam = idx->beam_regs, keep_lut = idx->lut_pad;
   int best_wpb = keep_wpb, best_hf = keep_hf, best_cw = 0, rc = QG_OK;
-  bool best_beam = true;
+  bool best_beam = true, best_lut = true;
   double best = -1.0;
   auto cleanup = [&]() {
     if (e0) (void)hipEventDestroy(e0);
@@ -671,6 +674,7 @@ static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bou
   // than the resident slots can finish sooner with fewer, less contended slots)
   idx->cu_waves = 0;
   idx->beam_regs = true;
+  idx->lut_pad = true;
   for (int wpb : {1, 2, 4, 8}) {
     for (int hf : {2, 3, 4}) {
       idx->wpb_pref = wpb;
@@ -710,35 +714,50 @@ static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bou
       best_beam = false;
     }
   }
+  if (!rc) {  // the LUT with packed rows, for the best setting so far
+    idx->cu_waves = best_cw;
+    idx->beam_regs = best_beam;
+    idx->lut_pad = false;
+    double t;
+    time_it(t);
+    if (!rc && t < best) {
+      best = t;
+      best_lut = false;
+    }
+  }
   cleanup();
   idx->wpb_pref = rc ? keep_wpb : best_wpb;
   idx->hash_factor = rc ? keep_hf : best_hf;
   idx->cu_waves = rc ? keep_cw : best_cw;
   idx->beam_regs = rc ? keep_beam : best_beam;
+  idx->lut_pad = rc ? keep_lut : best_lut;
   if (rc) return rc;
   if (out_wpb) *out_wpb = best_wpb;
   if (out_hash_factor) *out_hash_factor = best_hf;
   if (out_cu_waves) *out_cu_waves = best_cw;
   if (out_beam) *out_beam = best_beam ? 1 : 0;
+  if (out_lut) *out_lut = best_lut ? 1 : 0;
   if (out_ms) *out_ms = best;
   return QG_OK;
 }
 
 int qg_autotune(qg_index* idx, const float* queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                 int32_t* out_wpb, int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam,
-                double* out_ms) {
+                int32_t* out_lut, double* out_ms) {
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (nq <= 0 || !queries) return fail(QG_EINVAL, "autotuning needs queries");
   if (k < 1 || k > QG_MAX_K) return fail(QG_EINVAL, "k out of range");
   auto call = [&](int32_t* ids, float* dists) {
     return qg_search_ex(idx, queries, nq, k, ef, flags, ids, dists, nullptr);
   };
-  return autotune_impl(idx, nq, k, ef, false, call, out_wpb, out_hash_factor, out_cu_waves, out_beam, out_ms);
+  return autotune_impl(idx, nq, k, ef, false, call, out_wpb, out_hash_factor, out_cu_waves, out_beam, out_lut,
+                       out_ms);
 }
 
 int qg_autotune_mixed(qg_index* idx, const float* queries, int64_t nq, const int32_t* k_per_query,
                       const int32_t* ef_per_query, int32_t k_max, int32_t ef_max, int32_t flags, int32_t* out_wpb,
-                      int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam, double* out_ms) {
+                      int32_t* out_hash_factor, int32_t* out_cu_waves, int32_t* out_beam, int32_t* out_lut,
+                      double* out_ms) {
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (nq <= 0 || !queries || !k_per_query || !ef_per_query) return fail(QG_EINVAL, "autotuning needs queries");
   if (k_max < 1 || k_max > QG_MAX_K) return fail(QG_EINVAL, "k_max out of range");
@@ -746,16 +765,18 @@ int qg_autotune_mixed(qg_index* idx, const float* queries, int64_t nq, const int
     return qg_search_mixed(idx, queries, nq, k_per_query, ef_per_query, k_max, ef_max, flags, ids, dists, nullptr);
   };
   return autotune_impl(idx, nq, k_max, ef_max, true, call, out_wpb, out_hash_factor, out_cu_waves, out_beam,
-                       out_ms);
+                       out_lut, out_ms);
 }
 
-int qg_set_launch(qg_index* idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam) {
+int qg_set_launch(qg_index* idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam, int32_t lut) {
   if (!idx) return fail(QG_EINVAL, "index is NULL");
   if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(QG_EINVAL, "wavefronts per workgroup not 1, 2, 4 or 8");
   if (hash_factor < 2 || hash_factor > 4) return fail(QG_EINVAL, "hash factor not 2, 3 or 4");
   if (cu_waves < 0 || cu_waves > 64) return fail(QG_EINVAL, "resident wavefront cap out of range");
   if (beam != 0 && beam != 1) return fail(QG_EINVAL, "beam storage not 0 (LDS) or 1 (registers)");
+  if (lut != 0 && lut != 1) return fail(QG_EINVAL, "LUT layout not 0 (packed rows) or 1 (padded rows)");
   idx->beam_regs = beam == 1;
+  idx->lut_pad = lut == 1;
   idx->wpb_pref = wpb;
   idx->hash_factor = hash_factor;
   idx->cu_waves = cu_waves;
@@ -821,7 +842,8 @@ int qg_estimate(const qg_index* cidx, const float* queries, const int32_t* verte
   for (int32_t x : v)
     if (x < 0 || x >= idx->N) return fail(QG_EINVAL, "vertex id out of range");
   HIP_TRY(qgk::launch_rotate(queries, nq, idx->D, idx->rot, idx->qrot, nullptr, 0, idx->stream), "rotate");
-  qgk::EstimateArgs a{idx->blocks, idx->block_bytes, queries, idx->qrot, vertex_of_query, out_S, out_est, out_dist};
+  qgk::EstimateArgs a{idx->blocks, idx->block_bytes, queries, idx->qrot, vertex_of_query, out_S, out_est, out_dist,
+                      idx->lut_pad ? 1 : 0};
   HIP_TRY(qgk::launch_estimate(idx->D, idx->R, a, nq, idx->stream), "estimate");
   return QG_OK;
 }

@@ -14,6 +14,7 @@ struct SearchArgs {
   int64_t nq;
   int k, ef, k_cap, ef_cap;
   int hash_bits;  // LDS visited hash holds 2^hash_bits ids
+  int lut_pad;    // LUT layout: 1 = a padding row between lane groups, 0 = packed rows
   int flags;
   int entry;
   const int32_t* k_q;     // nullable: per-query k (then k is the bound)
@@ -46,6 +47,7 @@ struct EstimateArgs {
   int32_t* out_S;
   float* out_est;
   float* out_dist;
+  int lut_pad;  // LUT layout, as in SearchArgs
 };
 
 // Allocation-free search: size of the fixed per-device scratch array and its

@@ -317,10 +317,12 @@ __global__ __launch_bounds__(256) void encode_kernel(const float* __restrict__ X
 // Per-query quantisation and LUT (Sec. 2.2 FastScan with the query-only LUT
 // of Eq. 3.1b): m = max|q'_i|, inv = fl32(127/m), q_s = clamp(rint(q'_i*inv)),
 // Delta = fl32(m/127); LUT[k][p] = sum_t (bit t of p ? q_s[4k+t] : -q_s[4k+t]),
-// stored as int16 rows of 16, with one padding row before the second lane
-// group's rows when two lanes share a neighbour.  Returns Delta.
+// stored as int16 rows of 16.  Layout: with pad = 1 one padding row sits
+// before each later lane group's rows (when two lanes share a neighbour their
+// lookups then fall in different banks), with pad = 0 the rows are packed.
+// Returns Delta.
 template <int D, int R>
-__device__ __forceinline__ float build_lut(const float* __restrict__ qrot, int16_t* lut) {
+__device__ __forceinline__ float build_lut(const float* __restrict__ qrot, int16_t* lut, int pad) {
   constexpr int ROWS = D / 4;
   constexpr int RPG = D / 4 / (64 / R);
   const int lane = lane_id();
@@ -341,7 +343,7 @@ __device__ __forceinline__ float build_lut(const float* __restrict__ qrot, int16
       v = fminf(fmaxf(v, -127.0f), 127.0f);
       s[t] = (int)v;
     }
-    int16_t* row = lut + (k + k / RPG) * 16;
+    int16_t* row = lut + (k + pad * (k / RPG)) * 16;
 #pragma unroll
     for (int pp = 0; pp < 8; ++pp) {
       const int p = half * 8 + pp;
@@ -434,11 +436,11 @@ struct BlockView {
 
   // FastScan sum of this lane's nibbles; the LPN lanes of one neighbour are
   // then combined (integer, exact) so every lane holds S_j.
-  __device__ __forceinline__ int fastscan(const int16_t* lut, int lane) const {
+  __device__ __forceinline__ int fastscan(const int16_t* lut, int lane, int pad) const {
     constexpr int RPG = D / 4 / LPN;
     constexpr int UNIT_NIB = WORDS ? 8 : 4;
     const int h = lane % LPN;
-    const int16_t* base = lut + (h * RPG + h) * 16;  // group h starts after h padding rows
+    const int16_t* base = lut + (h * RPG + pad * h) * 16;  // group h starts after h padding rows (pad = 1)
     const uint32_t b8 = lds_addr(base);
     int s = 0;
 #pragma unroll
@@ -818,7 +820,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       return exact_dist<DPL>(qv, xv);
     }
   };
-  const float delta = build_lut<D, R>(a.qrot + q * D, lut);
+  const float delta = build_lut<D, R>(a.qrot + q * D, lut, a.lut_pad);
 
   // S starts with the entry, keyed by its exact distance (no estimate exists for it).
   float de;
@@ -930,7 +932,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const float dp = uni(dist(b.x));
 
     // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
-    const int S = b.fastscan(lut, lane);
+    const int S = b.fastscan(lut, lane, a.lut_pad);
     const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
     const uint32_t nb = (uint32_t)b.nb;
     const uint64_t cand = pack_kv(est, nb);
@@ -1302,7 +1304,7 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
       return exact_dist<DPL>(qv, xv);
     }
   };
-  const float delta = build_lut<D, R>(a.qrot + q * D, lut);
+  const float delta = build_lut<D, R>(a.qrot + q * D, lut, a.lut_pad);
 
   // the entry starts the beam, keyed by its exact distance; it is the first
   // vertex expanded, so its block serves both
@@ -1348,7 +1350,7 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
     uint32_t ns = vis.slot0(probe ? nb : 0u);
     uint32_t ne = vis.tab[ns];
     // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
-    const int S = b.fastscan(lut, lane);
+    const int S = b.fastscan(lut, lane, a.lut_pad);
     // finish the pending merge: range slots still holding the sentinel take
     // the candidates in rank order
     if (pending) {
@@ -1677,7 +1679,7 @@ __global__ __launch_bounds__(64) void estimate_kernel(EstimateArgs a) {
   const int lane = lane_id();
   const int64_t q = blockIdx.x;
   int16_t* lut = reinterpret_cast<int16_t*>(smem);
-  const float delta = build_lut<D, R>(a.qrot + q * D, lut);
+  const float delta = build_lut<D, R>(a.qrot + q * D, lut, a.lut_pad);
   float qv[BV::DPL];
   for (int t = 0; t < BV::DPL; ++t) {
     const int i = lane + 64 * t;
@@ -1686,7 +1688,7 @@ __global__ __launch_bounds__(64) void estimate_kernel(EstimateArgs a) {
   BV b;
   b.load(a.blocks + (int64_t)a.vertex[q] * a.block_bytes, lane);
   const float dp = exact_dist<BV::DPL>(qv, b.x);
-  const int S = b.fastscan(lut, lane);
+  const int S = b.fastscan(lut, lane, a.lut_pad);
   const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
   if (lane % BV::LPN == 0) {
     a.out_S[q * R + lane / BV::LPN] = S;

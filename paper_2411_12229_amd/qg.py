@@ -68,11 +68,12 @@ def _load():
         "qg_copy_blocks": ([P, i64, i64, P], c_int),
         "qg_set_stream": ([P, P], c_int),
         "qg_reserve": ([P, i64], c_int),
-        "qg_set_launch": ([P, i32, i32, i32, i32], c_int),
+        "qg_set_launch": ([P, i32, i32, i32, i32, i32], c_int),
         "qg_autotune": ([P, P, i64, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
-                         ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
+                         ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
         "qg_autotune_mixed": ([P, P, i64, P, P, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                               ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], c_int),
+                               ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                               ctypes.POINTER(ctypes.c_double)], c_int),
         "qg_index_info": ([P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i64)], c_int),
         "qg_timing": ([P, c_int], c_int),
@@ -146,12 +147,15 @@ class Index:
 
     def autotune(self, queries: torch.Tensor, k: int, ef: int, flags: int = 0):
         """Pick the launch shape (wavefronts per workgroup, visited-hash factor, cap on resident
-        wavefronts per compute unit, beam storage) by timing searches of these queries; returns
-        (wpb, hash_factor, cu_waves (0 = no cap), best ms per call, beam (1 = registers, 0 = LDS))."""
-        w, h, c, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        wavefronts per compute unit, beam storage, LUT layout) by timing searches of these queries; returns
+        (wpb, hash_factor, cu_waves (0 = no cap), best ms per call, beam (1 = registers, 0 = LDS),
+        lut (1 = padded rows, 0 = packed))."""
+        w, h, c, b, lu = (ctypes.c_int32() for _ in range(5))
+        ms = ctypes.c_double()
         _check(_lib.qg_autotune(self._h, _dev(queries, torch.float32, "queries"), queries.shape[0], k, ef, flags,
-                                ctypes.byref(w), ctypes.byref(h), ctypes.byref(c), ctypes.byref(b), ctypes.byref(ms)))
-        return w.value, h.value, c.value, ms.value, b.value
+                                ctypes.byref(w), ctypes.byref(h), ctypes.byref(c), ctypes.byref(b), ctypes.byref(lu),
+                                ctypes.byref(ms)))
+        return w.value, h.value, c.value, ms.value, b.value, lu.value
 
     def autotune_mixed(self, queries: torch.Tensor, k: torch.Tensor, ef: torch.Tensor, k_max: int, ef_max: int,
                        flags: int = 0):
@@ -159,16 +163,17 @@ class Index:
         nq = queries.shape[0]
         if k.shape != (nq,) or ef.shape != (nq,):
             raise ValueError("shape mismatch")
-        w, h, c, b, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        w, h, c, b, lu = (ctypes.c_int32() for _ in range(5))
+        ms = ctypes.c_double()
         _check(_lib.qg_autotune_mixed(self._h, _dev(queries, torch.float32, "queries"), nq,
                                       _dev(k, torch.int32, "k_per_query"), _dev(ef, torch.int32, "ef_per_query"),
                                       int(k_max), int(ef_max), flags, ctypes.byref(w), ctypes.byref(h),
-                                      ctypes.byref(c), ctypes.byref(b), ctypes.byref(ms)))
-        return w.value, h.value, c.value, ms.value, b.value
+                                      ctypes.byref(c), ctypes.byref(b), ctypes.byref(lu), ctypes.byref(ms)))
+        return w.value, h.value, c.value, ms.value, b.value, lu.value
 
-    def set_launch(self, wpb: int, hash_factor: int, cu_waves: int = 0, beam: int = 1) -> None:
+    def set_launch(self, wpb: int, hash_factor: int, cu_waves: int = 0, beam: int = 1, lut: int = 1) -> None:
         """Set the launch shape directly (the values qg_autotune picks)."""
-        _check(_lib.qg_set_launch(self._h, int(wpb), int(hash_factor), int(cu_waves), int(beam)))
+        _check(_lib.qg_set_launch(self._h, int(wpb), int(hash_factor), int(cu_waves), int(beam), int(lut)))
 
     def reserve(self, nq: int) -> None:
         """Size the query scratch for batches of up to nq queries (before capturing graphs)."""

@@ -42,13 +42,13 @@ def test_error_paths_without_device():
     assert lib.qg_search(None, None, 0, 10, 10, None, None) == -1
     assert lib.qg_search_mixed(None, None, ctypes.c_int64(4), None, None, 10, 10, 0, None, None, None) == -1
     assert lib.qg_reserve(None, ctypes.c_int64(10)) == -1
-    assert lib.qg_set_launch(None, 4, 3, 0, 1) == -1
+    assert lib.qg_set_launch(None, 4, 3, 0, 1, 1) == -1
     assert lib.qg_search_mixed_stop(None, None, ctypes.c_int64(0), None, None, 10, 10, 0, None, None, None,
                                     None) == -1
     assert lib.qg_server_set_stop(None, None) == -1
-    assert lib.qg_autotune(None, None, ctypes.c_int64(0), 10, 10, 0, None, None, None, None, None) == -1
+    assert lib.qg_autotune(None, None, ctypes.c_int64(0), 10, 10, 0, None, None, None, None, None, None) == -1
     assert lib.qg_autotune_mixed(None, None, ctypes.c_int64(0), None, None, 10, 10, 0, None, None, None, None,
-                                 None) == -1
+                                 None, None) == -1
     srv = ctypes.c_void_p(1)
     assert lib.qg_server_create(None, 2, 64, 10, 64, ctypes.byref(srv)) == -1 and srv.value is None
     assert lib.qg_server_submit(None, None, 1, 1, ctypes.c_uint64(0)) == -1

@@ -202,9 +202,11 @@ def test_autotune_keeps_results(cfg1, k, ef):
     idx = c["idx"]
     Qd = T(c["Q"])
     before = idx.search(Qd, k, ef, stats=True)
-    wpb, hf, cw, ms, beam = idx.autotune(Qd, k, ef)
-    print(f"autotune k={k} ef={ef}: wpb={wpb} hash factor={hf} cu waves={cw} beam={beam} {ms:.3f} ms", flush=True)
+    wpb, hf, cw, ms, beam, lut = idx.autotune(Qd, k, ef)
+    print(f"autotune k={k} ef={ef}: wpb={wpb} hash factor={hf} cu waves={cw} beam={beam} lut={lut} {ms:.3f} ms",
+          flush=True)
     assert wpb in (1, 2, 4, 8) and hf in (2, 3, 4) and cw in (0, 16, 20, 24) and beam in (0, 1) and ms > 0
+    assert lut in (0, 1)
     assert ef <= 128 or beam == 1  # larger beams are always in LDS; nothing to choose
     after = idx.search(Qd, k, ef, stats=True)
     torch.cuda.synchronize()
@@ -213,16 +215,16 @@ def test_autotune_keeps_results(cfg1, k, ef):
     oi, od = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], k, ef)
     assert np.array_equal(after[0].cpu().numpy(), oi) and np.array_equal(after[1].cpu().numpy(), od)
     # a shape set by hand: two wavefronts per workgroup, F = 4, at most 16 resident per compute unit
-    for beam_hand in (0, 1):
-        idx.set_launch(2, 4, 16, beam_hand)
+    for beam_hand, lut_hand in ((0, 1), (1, 0), (0, 0)):
+        idx.set_launch(2, 4, 16, beam_hand, lut_hand)
         hand = idx.search(Qd, k, ef, stats=True)
         torch.cuda.synchronize()
         for a, b in zip(before, hand):
             assert torch.equal(a, b)
-    for bad in ((3, 3, 0, 1), (4, 5, 0, 1), (4, 3, -1, 1), (4, 3, 65, 1), (4, 3, 0, 2)):
+    for bad in ((3, 3, 0, 1), (4, 5, 0, 1), (4, 3, -1, 1), (4, 3, 65, 1), (4, 3, 0, 2), (4, 3, 0, 1, 2)):
         with pytest.raises(qg.QGError):
             idx.set_launch(*bad)
-    idx.set_launch(wpb, hf, cw, beam)
+    idx.set_launch(wpb, hf, cw, beam, lut)
 
 
 def test_autotune_mixed_keeps_results(cfg1):
@@ -236,7 +238,7 @@ def test_autotune_mixed_keeps_results(cfg1):
     efs = rng.choice([16, 48, 160], nq).astype(np.int32)
     Qd, kd, efd = T(c["Q"][:nq]), T(ks), T(efs)
     before = c["idx"].search_mixed(Qd, kd, efd, k_max=100, ef_max=160, stats=True)
-    wpb, hf, cw, ms, beam = c["idx"].autotune_mixed(Qd, kd, efd, 100, 160)
+    wpb, hf, cw, ms, beam, lut = c["idx"].autotune_mixed(Qd, kd, efd, 100, 160)
     print(f"autotune mixed: wpb={wpb} hash factor={hf} cu waves={cw} beam={beam} {ms:.3f} ms", flush=True)
     assert wpb in (1, 2, 4, 8) and hf in (2, 3, 4) and cw in (0, 16, 20, 24) and beam == 1 and ms > 0
     after = c["idx"].search_mixed(Qd, kd, efd, k_max=100, ef_max=160, stats=True)
