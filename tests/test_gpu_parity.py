@@ -33,12 +33,16 @@ def say(msg):
 
 @pytest.fixture(scope="module")
 def cfg1():
+    """The small configuration: 10,000 vectors of the 16-cluster mixture, its
+    index graph built by the oracle's Algorithm 2 (R = 32, EF = 200, t = 3,
+    from seeded random initial and fill ids)."""
     X, Q = synth.gen_data(1)
     M = synth.rotation(128, synth.seed(1, "rotation"))
-    G = synth.knn_graph(X, 32, synth.seed(1, "long"))
     e = synth.medoid(X)
+    G = oracle.build_graph(X, 32, 200, 3, M, e, synth.random_graph(len(X), 32, synth.seed(1, "graph")),
+                           synth.random_graph(len(X), 32, synth.seed(1, "fill")))
     blocks = oracle.encode(X, G, M)
-    say("cfg1 index: N=10000 D=128 R=32")
+    say("cfg1 index: N=10000 D=128 R=32, oracle Algorithm 2 graph")
     idx = qg.qg_build_index(T(X), T(G), T(M), e)
     return dict(X=X, Q=Q, M=M, G=G, e=e, blocks=blocks, idx=idx)
 
@@ -117,7 +121,11 @@ def test_search_parity_cfg1(cfg1):
     orc = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], 10, 64, with_stats=True)
     _assert_same(gpu, orc, "cfg1")
     gt, _ = synth.ground_truth(c["X"], c["Q"], 10)
-    say(f"recall@10 = {synth.recall(gpu[0], gt, 10):.4f}")
+    rec = synth.recall(gpu[0], gt, 10)
+    say(f"recall@10 = {rec:.4f}")
+    # the 16-cluster mixture is isotropic within clusters (high local
+    # dimension): on this graph the oracle reaches 0.78 here
+    assert rec > 0.7
 
 
 @pytest.mark.parametrize("k,ef,nq", [(10, 16, 200), (1, 1, 3), (100, 100, 257), (10, 512, 64), (150, 7, 5),
