@@ -135,6 +135,10 @@ def worker_gaps(rec, lat, bat, arr):
                                 # CPU time the worker spent in it, and its context switches: a wall time far
                                 # above the CPU time with an involuntary switch means it was preempted
                                 "worker_cpu_ms": round(float(rec["enqueue_cpu_ms"][m]), 3),
+                                # its parts: staging and uploads, the search call, downloads and event
+                                "upload_ms": round(float(rec["upload_ms"][m]), 3),
+                                "search_call_ms": round(float(rec["search_ms"][m]), 3),
+                                "download_ms": round(float(rec["download_ms"][m]), 3),
                                 "voluntary_switches": int(rec["enqueue_nvcsw"][m]),
                                 "involuntary_switches": int(rec["enqueue_nivcsw"][m])},
             "enqueues_over_1ms": int(np.count_nonzero(enq > 1e-3)),

@@ -257,9 +257,10 @@ int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_wa
 /* ---- Serving loop (continuous batching) ----------------------------------
  * A server owns `streams` slots over one index.  Each slot has its own
  * stream, its own view of the index (the blocks are shared, the search
- * scratch is not) and pinned staging buffers for max_batch queries.  Requests
- * wait in classes of beam size (ef up to a power of two).  As soon as a slot
- * is free, a worker thread takes the class of the oldest waiting request and
+ * scratch is not), pinned staging buffers for max_batch queries and its own
+ * worker thread.  Requests wait in classes of beam size (ef up to a power of
+ * two).  As soon as a slot is free, its thread takes the class of the oldest
+ * waiting request and
  * every waiting request of that class (up to max_batch), and runs upload, one
  * qg_search_mixed launch sized for the batch's largest ef, and download on
  * that slot's stream.  Batches grow with the load, short searches never wait
@@ -314,6 +315,9 @@ typedef struct {
   float enqueue_cpu_ms;   /* CPU time the worker thread used between t_dispatch and t_enqueued */
   int32_t enqueue_nvcsw;  /* the worker's voluntary context switches in that interval (it blocked) */
   int32_t enqueue_nivcsw; /* its involuntary context switches in that interval (it was preempted) */
+  float upload_ms;        /* host time of the enqueue's parts: staging the queries and the uploads, */
+  float search_ms;        /* the search call (qg_search_mixed or qg_search_mixed_stop), */
+  float download_ms;      /* the downloads and the event */
 } qg_server_batch;
 
 /* Copy batch records [first, first + max) (host out[max]); the server keeps

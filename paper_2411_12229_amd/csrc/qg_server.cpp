@@ -1,9 +1,9 @@
 // qg_server.cpp -- a serving loop over one index (C ABI in include/qg.h).
 //
 // Requests (one query, its k and ef, a caller tag) are queued by any thread,
-// in classes of beam size (ef up to 2^c).  One worker thread owns S stream
-// slots; each slot has its own view of the index (shared blocks, private
-// scratch) and pinned staging buffers.  Whenever a slot is free the worker
+// in classes of beam size (ef up to 2^c).  The server has S stream slots, each
+// with its own view of the index (shared blocks, private scratch), pinned
+// staging buffers and worker thread.  Whenever a slot is free its worker
 // takes the class of the oldest waiting request, every waiting request of that
 // class (up to the batch limit), and enqueues on that slot's stream: the
 // queries' upload, one mixed search launch sized for the batch's largest ef
@@ -120,7 +120,7 @@ struct qg_server {
   int error = QG_OK;
   std::string errmsg;
   bool stop = false;
-  std::thread worker;
+  std::vector<std::thread> workers;  // one per slot
   std::thread producer;
 };
 
@@ -230,6 +230,7 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take, int slot) {
     fail_server(sv, "upload of a batch failed");
     return false;
   }
+  const double t_up = now_s();
   int32_t ef_batch = 1, k_batch = 1;
   double oldest = take[0].t_submit;
   for (int i = 0; i < n; ++i) {
@@ -245,6 +246,7 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take, int slot) {
     fail_server(sv, std::string("search: ") + qg_last_error());
     return false;
   }
+  const double t_se = now_s();
   if (hipMemcpyAsync(s.h_ids, s.d_ids, sizeof(int32_t) * K * n, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
       hipMemcpyAsync(s.h_dists, s.d_dists, sizeof(float) * K * n, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
       hipEventRecord(s.done, s.stream) != hipSuccess) {
@@ -253,6 +255,9 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take, int slot) {
   }
   rec.t_enqueued = now_s();
   const ThreadUsage u1 = ThreadUsage::now();
+  rec.upload_ms = (float)((t_up - rec.t_dispatch) * 1e3);
+  rec.search_ms = (float)((t_se - t_up) * 1e3);
+  rec.download_ms = (float)((rec.t_enqueued - t_se) * 1e3);
   rec.enqueue_cpu_ms = (float)((u1.cpu_s - u0.cpu_s) * 1e3);
   rec.enqueue_nvcsw = (int32_t)(u1.nvcsw - u0.nvcsw);
   rec.enqueue_nivcsw = (int32_t)(u1.nivcsw - u0.nivcsw);
@@ -273,111 +278,93 @@ bool dispatch(qg_server* sv, Slot& s, std::vector<Request>&& take, int slot) {
   return true;
 }
 
-void worker_loop(qg_server* sv) {
+// The worker thread of slot `si`: takes the class of the oldest waiting
+// request and every waiting request of that class (up to the batch limit),
+// enqueues the batch on its stream, waits for the batch's event and hands the
+// results out.  Each slot has its own thread, so a host call that takes long
+// in one slot (a copy call once held a thread for 5-11 ms) does not hold up
+// the batches of the others.
+void slot_loop(qg_server* sv, size_t si) {
   (void)hipSetDevice(sv->device);
+  Slot& s = sv->slots[si];
   const size_t K = (size_t)sv->k_max;
   for (;;) {
-    bool progressed = false, any_busy = false;
-    // completions
-    for (auto& s : sv->slots) {
-      if (!s.busy) continue;
-      const hipError_t e = hipEventQuery(s.done);
-      if (e == hipErrorNotReady) {
-        any_busy = true;
+    std::vector<Request> take;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      while (sv->npending == 0 && !sv->stop && sv->error == QG_OK) sv->cv.wait(lk);
+      if (sv->error != QG_OK) {
+        // a failed server completes nothing more: drop what waits
+        for (auto& d : sv->pending) d.clear();
+        sv->npending = 0;
+        sv->cv_done.notify_all();
+        if (sv->stop) return;
+        sv->cv.wait(lk);
         continue;
       }
-      if (e != hipSuccess) {
-        fail_server(sv, std::string("batch failed: ") + hipGetErrorString(e));
-        s.busy = false;
-        continue;
+      if (sv->npending == 0) return;  // stopping, nothing left
+      int c = -1;  // the class of the oldest waiting request
+      for (int i = 0; i < qg_server::kClasses; ++i)
+        if (!sv->pending[i].empty() && (c < 0 || sv->pending[i].front().t_submit < sv->pending[c].front().t_submit))
+          c = i;
+      auto& q = sv->pending[c];
+      while (!q.empty() && (int)take.size() < sv->max_batch) {
+        take.push_back(std::move(q.front()));
+        q.pop_front();
       }
-      const double t = now_s();
-      float dev_ms = -1.0f;
-      if (hipEventElapsedTime(&dev_ms, s.start, s.done) != hipSuccess) dev_ms = -1.0f;
-      const size_t n = s.batch.size();
-      DoneBatch db;  // built outside the lock: one record per batch, reusing a polled one's storage
-      {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (!sv->spare.empty()) {
-          db = std::move(sv->spare.back());
-          sv->spare.pop_back();
-        }
-      }
-      db.next = db.pos = 0;
-      db.seq = s.seq;
-      db.tags.resize(n);
-      db.ks.resize(n);
-      db.latency.resize(n);
-      db.ids.clear();
-      db.dists.clear();
-      for (size_t i = 0; i < n; ++i) {
-        db.tags[i] = s.batch[i].tag;
-        db.ks[i] = s.batch[i].k;
-        db.latency[i] = t - s.batch[i].t_submit;
-        const size_t k = (size_t)s.batch[i].k;
-        db.ids.insert(db.ids.end(), s.h_ids + i * K, s.h_ids + i * K + k);
-        db.dists.insert(db.dists.end(), s.h_dists + i * K, s.h_dists + i * K + k);
-      }
-      s.batch.clear();
+      const size_t n = take.size();
+      sv->npending -= (int64_t)n;
+      ++sv->batches;
+      sv->largest = std::max<int64_t>(sv->largest, (int64_t)n);
+      if (sv->npending > 0) sv->cv.notify_one();  // more waits: wake another free slot
+    }
+    if (!dispatch(sv, s, std::move(take), (int)si)) continue;
+    hipError_t e;
+    while ((e = hipEventQuery(s.done)) == hipErrorNotReady) std::this_thread::yield();
+    if (e != hipSuccess) {
+      fail_server(sv, std::string("batch failed: ") + hipGetErrorString(e));
       s.busy = false;
-      progressed = true;
-      {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (s.seq >= 0) {
-          sv->records[(size_t)s.seq].t_done = t;
-          sv->records[(size_t)s.seq].device_ms = dev_ms;
-        }
-        sv->done.push_back(std::move(db));
-        sv->completed += (int64_t)n;
-      }
-      sv->cv_done.notify_all();
+      continue;
     }
-    // dispatch whatever waits onto a free slot
-    for (size_t si = 0; si < sv->slots.size(); ++si) {
-      Slot& s = sv->slots[si];
-      if (s.busy) continue;
-      std::vector<Request> take;
-      {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->error != QG_OK) break;
-        int c = -1;  // the class of the oldest waiting request
-        for (int i = 0; i < qg_server::kClasses; ++i)
-          if (!sv->pending[i].empty() && (c < 0 || sv->pending[i].front().t_submit < sv->pending[c].front().t_submit))
-            c = i;
-        if (c >= 0) {
-          auto& q = sv->pending[c];
-          while (!q.empty() && (int)take.size() < sv->max_batch) {
-            take.push_back(std::move(q.front()));
-            q.pop_front();
-          }
-        }
-        const size_t n = take.size();
-        sv->npending -= (int64_t)n;
-        if (n) {
-          ++sv->batches;
-          sv->largest = std::max<int64_t>(sv->largest, (int64_t)n);
-        }
-      }
-      if (take.empty()) break;
-      if (!dispatch(sv, s, std::move(take), (int)si)) break;
-      any_busy = progressed = true;
-    }
-    std::unique_lock<std::mutex> lk(sv->mu);
-    if (sv->stop && sv->npending == 0 && !any_busy) break;
-    if (sv->error != QG_OK && !any_busy) {
-      // a failed server completes nothing more: drop what waits
-      for (auto& d : sv->pending) d.clear();
-      sv->npending = 0;
-      if (sv->stop) break;
-    }
-    if (!progressed) {
-      if (any_busy) {
-        lk.unlock();
-        std::this_thread::yield();  // a batch is in flight: poll its event again soon
-      } else if (sv->npending == 0 && !sv->stop) {
-        sv->cv.wait_for(lk, std::chrono::milliseconds(50));
+    const double t = now_s();
+    float dev_ms = -1.0f;
+    if (hipEventElapsedTime(&dev_ms, s.start, s.done) != hipSuccess) dev_ms = -1.0f;
+    const size_t n = s.batch.size();
+    DoneBatch db;  // built outside the lock: one record per batch, reusing a polled one's storage
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      if (!sv->spare.empty()) {
+        db = std::move(sv->spare.back());
+        sv->spare.pop_back();
       }
     }
+    db.next = db.pos = 0;
+    db.seq = s.seq;
+    db.tags.resize(n);
+    db.ks.resize(n);
+    db.latency.resize(n);
+    db.ids.clear();
+    db.dists.clear();
+    for (size_t i = 0; i < n; ++i) {
+      db.tags[i] = s.batch[i].tag;
+      db.ks[i] = s.batch[i].k;
+      db.latency[i] = t - s.batch[i].t_submit;
+      const size_t k = (size_t)s.batch[i].k;
+      db.ids.insert(db.ids.end(), s.h_ids + i * K, s.h_ids + i * K + k);
+      db.dists.insert(db.dists.end(), s.h_dists + i * K, s.h_dists + i * K + k);
+    }
+    s.batch.clear();
+    s.busy = false;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      if (s.seq >= 0) {
+        sv->records[(size_t)s.seq].t_done = t;
+        sv->records[(size_t)s.seq].device_ms = dev_ms;
+      }
+      sv->done.push_back(std::move(db));
+      sv->completed += (int64_t)n;
+    }
+    sv->cv_done.notify_all();
   }
 }
 
@@ -413,7 +400,7 @@ int qg_server_create(qg_index* idx, int32_t streams, int32_t max_batch, int32_t 
     delete sv;
     return qgi::set_error(QG_ENOMEM, "server buffers or streams");
   }
-  sv->worker = std::thread(worker_loop, sv);
+  for (size_t i = 0; i < sv->slots.size(); ++i) sv->workers.emplace_back(slot_loop, sv, i);
   *out = sv;
   return QG_OK;
 }
@@ -597,7 +584,8 @@ void qg_server_destroy(qg_server* sv) {
     sv->stop = true;
   }
   sv->cv.notify_all();
-  if (sv->worker.joinable()) sv->worker.join();
+  for (auto& w : sv->workers)
+    if (w.joinable()) w.join();
   int old = 0;
   (void)hipGetDevice(&old);
   (void)hipSetDevice(sv->device);

@@ -495,7 +495,8 @@ class Server:
                              ("t_done", np.float64), ("device_ms", np.float32), ("n", np.int32),
                              ("ef_max", np.int32), ("k_max", np.int32), ("slot", np.int32),
                              ("enqueue_cpu_ms", np.float32), ("enqueue_nvcsw", np.int32),
-                             ("enqueue_nivcsw", np.int32)],
+                             ("enqueue_nivcsw", np.int32), ("upload_ms", np.float32), ("search_ms", np.float32),
+                             ("download_ms", np.float32)],
                             align=True)  # the C struct's layout, padded to its doubles' alignment
 
     def batches(self, first: int = 0, max_records: int = 1 << 22) -> np.ndarray:
