@@ -1097,7 +1097,17 @@ def ls_study(args, dev):
                     log(f"[ls-study] target {target} learned stop: {row}")
                     if best is None or q > best["qps"]:
                         best = row
+        # the bound for any stop evaluated every 4 expansions (each query stops at the first point whose top-k
+        # already has its final recall), on the test queries, at the fixed beam and at the stop's beam
+        ideal = []
+        for e_b in dict.fromkeys([fx["ef"]] + ([best["ef"]] if best else [])):
+            with torch.cuda.stream(stream):
+                e_ideal, e_full = learned_stop.ideal_stop(idx, Qs, torch.from_numpy(gt).to(dev), k, e_b, t_min, 4)
+            ideal.append({"ef": e_b, "mean_expansions_ideal_stop": round(e_ideal, 2),
+                          "mean_expansions_full_search": round(e_full, 2)})
+        log(f"[ls-study] target {target} ideal stop: {ideal}")
         rows.append({"target": target, "fixed": fx, "fixed_picked_on_held_out": fx_ho, "learned_stop": best,
+                     "ideal_stop": ideal,
                      "speedup_vs_held_out_fixed": round(best["qps"] / fx_ho["qps"], 3) if best and fx_ho else None,
                      "speedup_vs_test_tuned_fixed": round(best["qps"] / fx["qps"], 3) if best else None})
     wl = ("SIFT-shaped 1M x 128" if c == synth.SIFT_LIKE else

@@ -40,6 +40,25 @@ def collect(idx, queries: torch.Tensor, gt: torch.Tensor, k: int, ef: int, t_min
     return feat[valid], label[valid]
 
 
+def ideal_stop(idx, queries: torch.Tensor, gt: torch.Tensor, k: int, ef: int, t_min: int, t_every: int,
+               trace_max: int = 256):
+    """The bound any stop rule evaluated at these points can reach: each query stops at the first evaluation
+    point whose top-k already has the recall the full search ends with (recall unchanged).  Returns (mean
+    expansions with that stop, mean expansions of the full search)."""
+    ids, _, st, tr = idx.search_stop(queries, k, ef, None, t_min=t_min, t_every=t_every, trace_max=trace_max,
+                                     stats=True)
+    _, nn, _, cnt = tr
+    final = recall_rows(ids, gt)
+    rec = recall_rows(nn, gt)
+    T = nn.shape[1]
+    pts = torch.arange(T, device=nn.device)
+    done = (rec >= final[:, None]) & (pts[None, :] < cnt[:, None])
+    first = torch.where(done.any(1), done.float().argmax(1), torch.full_like(cnt, T).long())
+    full = st[:, 0].float()
+    at = torch.where(first < T, (t_min + first * t_every).float(), full)
+    return torch.minimum(at, full).mean().item(), full.mean().item()
+
+
 class StopMLP(torch.nn.Module):
     def __init__(self):
         super().__init__()
