@@ -53,8 +53,8 @@ static int cmp_dbl(const void *a, const void *b) {
 }
 
 /* NSG edge selection on candidates sorted by distance to u: scan in order and
- * keep v unless an already kept w is closer to v than u is (Sec. 3.2.1,
- * "the pruning rule of NSG"), until R are kept.  kept[] receives candidate
+ * keep v unless an already kept w is closer to v than u is (Sec. 3.2.1: the
+ * rule NSG prunes with), until R are kept.  kept[] receives candidate
  * indices; returns the count. */
 static int nsg_prune(const float *X, int D, const cand_t *c, int nc, int R, int *kept) {
   int nk = 0;
@@ -154,8 +154,10 @@ static int64_t bfs(const int32_t *G, int64_t N, int R, int32_t entry, char *seen
  *    Algorithm 1 run for x_u with beam EF on the current graph, together with
  *    u's current neighbours (the old list is reconsidered, not retained),
  *    minus u itself;
- *  - "adjust G" replaces every list at once after all vertices are pruned;
- *  - refinement (line 9) runs on the last iteration's candidates;
+ *  - the graph takes every vertex's new list at once, after all vertices
+ *    are pruned;
+ *  - refinement (the step of Algorithm 2 after its iterations) runs on the
+ *    last iteration's candidates;
  *  - an addition: vertices unreachable from the entry are linked, in rounds,
  *    from the nearest reachable vertex their search finds (its empty slot,
  *    else its farthest edge), since the NSG rule leaves vertices that no list

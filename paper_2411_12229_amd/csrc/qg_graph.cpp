@@ -4,7 +4,7 @@
 // data of every vertex), searches every vector with Algorithm 1 (beam EF, EF
 // results) through the same search kernels as queries, turns the results and
 // the current neighbours into sorted candidate lists, and applies the NSG
-// pruning rule; "adjust G" replaces all lists at once.  Then the refinement
+// pruning rule; every list is replaced at once.  Then the refinement
 // supplements edges up to R, random ids fill vertices with too few candidates,
 // and unreachable vertices are linked from their nearest reachable vertex.
 #include <hip/hip_runtime.h>

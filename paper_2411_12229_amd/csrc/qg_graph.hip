@@ -46,7 +46,7 @@ __device__ __forceinline__ bool cand_greater(double da, int32_t ia, double db, i
   return da > db || (da == db && ia > ib);
 }
 
-// Candidates of vertex u (Alg. 2, "search on G to find candidates"): the
+// Candidates of vertex u (Alg. 2, the search step of each iteration): the
 // search results for x_u that are not u, then u's current neighbours not among
 // them and not u; each with its exact squared distance to u; sorted by
 // (distance, id).  One wavefront per vertex of the chunk; P = the candidate
