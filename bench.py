@@ -199,7 +199,8 @@ def main():
                     help="time the default launch shape instead of the one qg_autotune picks for the benchmark queries")
     ap.add_argument("--launch", default="",
                     help="wpb,hash_factor,cu_waves[,beam[,lut]]: set this launch shape (beam 1: in registers where "
-                         "the beam size allows, the default; 0: in LDS; lut 1: padded rows, the default; 0: packed) "
+                         "the beam size allows, the default; 0: in LDS; lut bit 0: padded rows, bit 1: int32 "
+                         "entries, 1 the default) "
                          "for every search instead of autotuning")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--ablation", action="store_true", help="also sweep the w/o ME ablation (Sec. 4.2.3)")
@@ -363,13 +364,13 @@ def main():
             idx.search(Qs, k, ef)
 
     tuned = {"waves_per_workgroup": shape[0], "hash_factor": shape[1], "resident_waves_per_cu_cap": shape[2],
-             "beam_in_registers": shape[3], "lut_padded_rows": shape[4], "set_by": "--launch"} if args.launch else None
+             "beam_in_registers": shape[3], "lut_layout": shape[4], "set_by": "--launch"} if args.launch else None
     if not args.no_autotune and not args.launch:
         with torch.cuda.stream(stream):
             wpb_t, hf_t, cw_t, tms, beam_t, lut_t = idx.autotune(Qs, k, ef)
         shape = (wpb_t, hf_t, cw_t, beam_t, lut_t)
         tuned = {"waves_per_workgroup": wpb_t, "hash_factor": hf_t, "resident_waves_per_cu_cap": cw_t,
-                 "beam_in_registers": beam_t, "lut_padded_rows": lut_t, "median_call_ms": round(tms, 4)}
+                 "beam_in_registers": beam_t, "lut_layout": lut_t, "median_call_ms": round(tms, 4)}
         log(f"[bench] autotune: {tuned}")
     qps, ms_per_step, kern_ms, rot_ms = timed(plain)
     expansions = int(s[:, 0].sum())

@@ -220,15 +220,17 @@ int qg_set_stream(qg_index *idx, void *hip_stream);
  * than the resident query slots can finish sooner on fewer, less contended
  * slots), then, for beams of at most 128 entries, the beam kept in LDS
  * against the beam kept in registers, then the LUT layout (the per-query
- * table of Sec. 2.2's FastScan, int16 rows of 16 entries: a padding row
- * between the lane groups that share a neighbour, so their lookups fall in
- * different LDS banks, against packed rows).  The fastest setting is kept for
+ * table of Sec. 2.2's FastScan, rows of 16 entries: int16 or int32 entries,
+ * with a padding row between the lane groups that share a neighbour, so that
+ * their lookups fall in different LDS banks, or with packed rows; int32
+ * entries apply to the plain and mixed searches).  The fastest setting is kept for
  * later searches of this index.  Each setting is timed as the median of seven
  * calls after one untimed call.  Results do not depend on the choice, only
  * the speed.  Outputs (host, nullable): the chosen wavefronts per workgroup,
  * F, the cap (0 = none), the beam storage (1 = registers where the beam size
- * allows, 0 = LDS), the LUT layout (1 = padded rows, 0 = packed) and the
- * median time in ms of one qg_search_ex call in that setting.
+ * allows, 0 = LDS), the LUT layout (bit 0: padded rows, bit 1: int32
+ * entries; 1 = padded int16, the default) and the median time in ms of one
+ * qg_search_ex call in that setting.
  * Synchronous; allocates and frees temporary outputs. */
 int qg_autotune(qg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t ef, int32_t flags,
                 int32_t *out_wpb, int32_t *out_hash_factor, int32_t *out_cu_waves, int32_t *out_beam,
@@ -249,9 +251,9 @@ int qg_autotune_mixed(qg_index *idx, const float *queries, int64_t nq, const int
  * workgroup (1, 2, 4 or 8), visited-hash factor F (2, 3 or 4), the cap on
  * resident wavefronts per compute unit (0 = none, at most 64), the beam
  * storage (1: in registers for beams of at most 128 entries, the default;
- * 0: always in LDS) and the LUT layout (1: padded rows, the default; 0:
- * packed rows).  Results do not depend on it.  QG_EINVAL for values outside
- * these sets. */
+ * 0: always in LDS) and the LUT layout (0..3; bit 0: padded rows, bit 1:
+ * int32 entries; 1, padded int16 rows, is the default).  Results do not
+ * depend on it.  QG_EINVAL for values outside these sets. */
 int qg_set_launch(qg_index *idx, int32_t wpb, int32_t hash_factor, int32_t cu_waves, int32_t beam, int32_t lut);
 
 /* ---- Serving loop (continuous batching) ----------------------------------

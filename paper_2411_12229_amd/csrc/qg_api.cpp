@@ -86,6 +86,7 @@ struct qg_index {
   int cus = 256;     // compute units of the device (read at creation; sizes the persistent grid)
   bool beam_regs = true;  // beams of at most 128 entries live in registers (else in LDS)
   bool lut_pad = true;    // LUT layout: a padding row between lane groups (else packed rows)
+  bool lut32 = false;     // LUT entries int32 (else int16), for the plain and mixed main pass
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev[2];  // pairs per kernel class
@@ -197,6 +198,7 @@ qg_index* make_view(const qg_index* base) {
   v->wpb_pref = base->wpb_pref;
   v->hash_factor = base->hash_factor;
   v->lut_pad = base->lut_pad;
+  v->lut32 = base->lut32;
   v->cu_waves = base->cu_waves;
   v->cus = base->cus;
   v->beam_regs = base->beam_regs;
@@ -568,7 +570,10 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
     a.tr_count = stop->trace_count;
   }
 
-  const qgl::SearchLds L = qgl::search_lds(idx->D, idx->R, ef_cap, 1 << hbits, k_cap);
+  // LUT entries: int32 when chosen, for the main pass of the plain and mixed
+  // modes (the overflow pass and the other modes keep int16)
+  const int lb = (idx->lut32 && (ls == 0 || ls == 3)) ? 4 : 2;
+  const qgl::SearchLds L = qgl::search_lds(idx->D, idx->R, ef_cap, 1 << hbits, k_cap, lb);
   const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
   const size_t lds_cap = 160 * 1024;
   const bool mlp_lds = ls == 1 || ls == 4;
@@ -578,7 +583,7 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   if ((size_t)L.total + extra > lds_cap) return fail(QG_EUNSUPPORTED, "per-query LDS exceeds the device limit");
   const size_t lds = (size_t)wpb * L.total + extra;
   const int nb = (idx->beam_regs && !(flags & QG_SEARCH_LDS_BEAM)) ? qgk::beam_regs(false, ls, ef, idx->N) : 0;
-  int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, nb, wpb, lds);
+  int occ = qgk::search_occupancy(idx->D, idx->R, false, ls, nb, lb, wpb, lds);
   if (occ <= 0) occ = 1;
   if (idx->cu_waves > 0) occ = std::min(occ, std::max(1, idx->cu_waves / wpb));
   int64_t want = (nq + wpb - 1) / wpb;
@@ -591,10 +596,11 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
           "rotate queries");
   if (!fx && (rc = record(idx, 0, false))) return rc;
   if (!fx && (rc = record(idx, 1, true))) return rc;
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, nb, a, grid, wpb, lds, idx->stream), "search");
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, false, ls, nb, lb, a, grid, wpb, lds, idx->stream), "search");
   if (!fx && (rc = record(idx, 1, false))) return rc;
   // overflow pass: one wavefront per workgroup, one bitset each
-  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, 0, a, idx->fb_slots, 1, (size_t)Lf.total + extra, idx->stream),
+  HIP_TRY(qgk::launch_search(idx->D, idx->R, true, ls, 0, 2, a, idx->fb_slots, 1, (size_t)Lf.total + extra,
+                             idx->stream),
           "search overflow pass");
   return QG_OK;
 }
@@ -635,9 +641,9 @@ static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bou
   float* dists = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int keep_wpb = idx->wpb_pref, keep_hf = idx->hash_factor, keep_cw = idx->cu_waves;
-  const bool keep_beam = idx->beam_regs, keep_lut = idx->lut_pad;
+  const bool keep_beam = idx->beam_regs, keep_lut = idx->lut_pad, keep_lut32 = idx->lut32;
   int best_wpb = keep_wpb, best_hf = keep_hf, best_cw = 0, rc = QG_OK;
-  bool best_beam = true, best_lut = true;
+  bool best_beam = true, best_lut = true, best_lut32 = false;
   double best = -1.0;
   auto cleanup = [&]() {
     if (e0) (void)hipEventDestroy(e0);
@@ -675,6 +681,7 @@ static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bou
   idx->cu_waves = 0;
   idx->beam_regs = true;
   idx->lut_pad = true;
+  idx->lut32 = false;
   for (int wpb : {1, 2, 4, 8}) {
     for (int hf : {2, 3, 4}) {
       idx->wpb_pref = wpb;
@@ -714,15 +721,20 @@ static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bou
       best_beam = false;
     }
   }
-  if (!rc) {  // the LUT with packed rows, for the best setting so far
+  // the other LUT layouts (packed int16 rows, padded and packed int32 rows)
+  // for the best setting so far
+  for (int layout : {0, 3, 2}) {
+    if (rc) break;
     idx->cu_waves = best_cw;
     idx->beam_regs = best_beam;
-    idx->lut_pad = false;
+    idx->lut_pad = (layout & 1) != 0;
+    idx->lut32 = (layout & 2) != 0;
     double t;
     time_it(t);
     if (!rc && t < best) {
       best = t;
-      best_lut = false;
+      best_lut = idx->lut_pad;
+      best_lut32 = idx->lut32;
     }
   }
   cleanup();
@@ -731,12 +743,13 @@ static int autotune_impl(qg_index* idx, int64_t nq, int32_t kcap, int32_t ef_bou
   idx->cu_waves = rc ? keep_cw : best_cw;
   idx->beam_regs = rc ? keep_beam : best_beam;
   idx->lut_pad = rc ? keep_lut : best_lut;
+  idx->lut32 = rc ? keep_lut32 : best_lut32;
   if (rc) return rc;
   if (out_wpb) *out_wpb = best_wpb;
   if (out_hash_factor) *out_hash_factor = best_hf;
   if (out_cu_waves) *out_cu_waves = best_cw;
   if (out_beam) *out_beam = best_beam ? 1 : 0;
-  if (out_lut) *out_lut = best_lut ? 1 : 0;
+  if (out_lut) *out_lut = (best_lut ? 1 : 0) | (best_lut32 ? 2 : 0);
   if (out_ms) *out_ms = best;
   return QG_OK;
 }
@@ -774,9 +787,10 @@ int qg_set_launch(qg_index* idx, int32_t wpb, int32_t hash_factor, int32_t cu_wa
   if (hash_factor < 2 || hash_factor > 4) return fail(QG_EINVAL, "hash factor not 2, 3 or 4");
   if (cu_waves < 0 || cu_waves > 64) return fail(QG_EINVAL, "resident wavefront cap out of range");
   if (beam != 0 && beam != 1) return fail(QG_EINVAL, "beam storage not 0 (LDS) or 1 (registers)");
-  if (lut != 0 && lut != 1) return fail(QG_EINVAL, "LUT layout not 0 (packed rows) or 1 (padded rows)");
+  if (lut < 0 || lut > 3) return fail(QG_EINVAL, "LUT layout not in 0..3 (bit 0: padded rows, bit 1: int32)");
   idx->beam_regs = beam == 1;
-  idx->lut_pad = lut == 1;
+  idx->lut_pad = (lut & 1) != 0;
+  idx->lut32 = (lut & 2) != 0;
   idx->wpb_pref = wpb;
   idx->hash_factor = hash_factor;
   idx->cu_waves = cu_waves;

@@ -70,9 +70,9 @@ hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, con
 // nb: beam registers per lane (0: beam in LDS; 1, 2: ef up to 64, 128), as
 // beam_regs() picks for the pass, mode, bound on ef and vector count.
 int beam_regs(bool overflow_pass, int ls_mode, int ef_bound, int64_t n);
-hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, int nb, const SearchArgs& a, int grid,
+hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, int nb, int lb, const SearchArgs& a, int grid,
                          int wpb, size_t lds, hipStream_t st);
-int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int nb, int wpb, size_t lds);
+int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int nb, int lb, int wpb, size_t lds);
 constexpr size_t mlp_lds_bytes() { return 2 * 64 * 16 + 8 * 64 * 16 + 3 * 128 + 16; }
 hipError_t launch_estimate(int D, int R, const EstimateArgs& a, int64_t nq, hipStream_t st);
 

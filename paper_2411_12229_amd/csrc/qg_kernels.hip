@@ -320,9 +320,10 @@ __global__ __launch_bounds__(256) void encode_kernel(const float* __restrict__ X
 // stored as int16 rows of 16.  Layout: with pad = 1 one padding row sits
 // before each later lane group's rows (when two lanes share a neighbour their
 // lookups then fall in different banks), with pad = 0 the rows are packed.
-// Returns Delta.
-template <int D, int R>
-__device__ __forceinline__ float build_lut(const float* __restrict__ qrot, int16_t* lut, int pad) {
+// Entries are int16 (LB = 2) or int32 (LB = 4, the same values).  Returns
+// Delta.
+template <int D, int R, int LB = 2>
+__device__ __forceinline__ float build_lut(const float* __restrict__ qrot, void* lut, int pad) {
   constexpr int ROWS = D / 4;
   constexpr int RPG = D / 4 / (64 / R);
   const int lane = lane_id();
@@ -343,14 +344,17 @@ __device__ __forceinline__ float build_lut(const float* __restrict__ qrot, int16
       v = fminf(fmaxf(v, -127.0f), 127.0f);
       s[t] = (int)v;
     }
-    int16_t* row = lut + (k + pad * (k / RPG)) * 16;
+    const int r = k + pad * (k / RPG);
 #pragma unroll
     for (int pp = 0; pp < 8; ++pp) {
       const int p = half * 8 + pp;
       int acc = 0;
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc += ((p >> t) & 1) ? s[t] : -s[t];
-      row[p] = (int16_t)acc;
+      if constexpr (LB == 4)
+        static_cast<int32_t*>(lut)[r * 16 + p] = acc;
+      else
+        static_cast<int16_t*>(lut)[r * 16 + p] = (int16_t)acc;
     }
   }
   wave_sync();
@@ -385,13 +389,19 @@ __device__ __forceinline__ uint32_t add_byte(uint32_t base, uint32_t x) {
 }
 
 // Sum of the LUT entries of nibbles T .. N-1 of one code unit: nibble t of
-// the unit indexes row t, at byte (t >> 1) of ev (even t) or od (odd t).
-template <int T, int N>
+// the unit indexes row t (16 entries of LB bytes), at byte (t >> 1) of ev
+// (even t) or od (odd t), which hold the nibbles times LB.
+typedef __attribute__((address_space(3))) const int32_t lds_i32;
+template <int T, int N, int LB>
 __device__ __forceinline__ int lut_sum(uint32_t b8, uint32_t ev, uint32_t od) {
   const uint32_t a = add_byte<(T >> 1)>(b8, (T & 1) ? od : ev);
-  const int v = *(lds_i16*)(uintptr_t)(a + T * 32);
+  int v;
+  if constexpr (LB == 4)
+    v = *(lds_i32*)(uintptr_t)(a + T * 64);
+  else
+    v = *(lds_i16*)(uintptr_t)(a + T * 32);
   if constexpr (T + 1 < N)
-    return v + lut_sum<T + 1, N>(b8, ev, od);
+    return v + lut_sum<T + 1, N, LB>(b8, ev, od);
   else
     return v;
 }
@@ -436,19 +446,21 @@ struct BlockView {
 
   // FastScan sum of this lane's nibbles; the LPN lanes of one neighbour are
   // then combined (integer, exact) so every lane holds S_j.
-  __device__ __forceinline__ int fastscan(const int16_t* lut, int lane, int pad) const {
+  template <int LB = 2>
+  __device__ __forceinline__ int fastscan(const void* lut, int lane, int pad) const {
     constexpr int RPG = D / 4 / LPN;
     constexpr int UNIT_NIB = WORDS ? 8 : 4;
     const int h = lane % LPN;
-    const int16_t* base = lut + (h * RPG + pad * h) * 16;  // group h starts after h padding rows (pad = 1)
-    const uint32_t b8 = lds_addr(base);
+    // group h starts after h padding rows (pad = 1)
+    const uint32_t b8 = lds_addr(static_cast<const int16_t*>(lut)) + (uint32_t)((h * RPG + pad * h) * 16 * LB);
     int s = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      // byte offsets (2 x nibble) of the even and odd nibbles, one per byte:
+      // byte offsets (LB x nibble) of the even and odd nibbles, one per byte:
       // each lookup address is the base plus one byte of a register
-      const uint32_t ev = (cw[w] << 1) & 0x1E1E1E1Eu, od = (cw[w] >> 3) & 0x1E1E1E1Eu;
-      s += lut_sum<0, UNIT_NIB>(b8 + w * UNIT_NIB * 32, ev, od);
+      const uint32_t ev = LB == 4 ? (cw[w] << 2) & 0x3C3C3C3Cu : (cw[w] << 1) & 0x1E1E1E1Eu;
+      const uint32_t od = LB == 4 ? (cw[w] >> 2) & 0x3C3C3C3Cu : (cw[w] >> 3) & 0x1E1E1E1Eu;
+      s += lut_sum<0, UNIT_NIB, LB>(b8 + w * UNIT_NIB * 16 * LB, ev, od);
       // wide codes: keep the lookups of one unit together, so that not all of
       // them are in flight (and in registers) at once
       if constexpr (NW > 4) {
@@ -747,7 +759,7 @@ __device__ __forceinline__ uint64_t pick(const uint64_t (&b)[NB], int r) {
   return v;
 }
 
-template <int D, int R, bool GV, int LS>
+template <int D, int R, bool GV, int LS, int LB>
 __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L, uint32_t* gbits,
                            const uint8_t* mlp) {
   using BV = BlockView<D, R>;
@@ -769,7 +781,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       return;
     }
   }
-  int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
+  void* lut = lds + L.lut;
   // beam entries: sortable(key) << 32 | id | checked, kept in ascending order
   uint64_t* beam = reinterpret_cast<uint64_t*>(lds + L.beam);
   uint32_t* beam_lo = reinterpret_cast<uint32_t*>(lds + L.beam);  // low words (id | checked)
@@ -820,7 +832,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
       return exact_dist<DPL>(qv, xv);
     }
   };
-  const float delta = build_lut<D, R>(a.qrot + q * D, lut, a.lut_pad);
+  const float delta = build_lut<D, R, LB>(a.qrot + q * D, lut, a.lut_pad);
 
   // S starts with the entry, keyed by its exact distance (no estimate exists for it).
   float de;
@@ -932,7 +944,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
     const float dp = uni(dist(b.x));
 
     // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
-    const int S = b.fastscan(lut, lane, a.lut_pad);
+    const int S = b.template fastscan<LB>(lut, lane, a.lut_pad);
     const float est = __builtin_fmaf(b.fr, (float)S * delta, b.fa + dp);
     const uint32_t nb = (uint32_t)b.nb;
     const uint64_t cand = pack_kv(est, nb);
@@ -1243,7 +1255,7 @@ __device__ void search_one(const SearchArgs& a, int64_t q, uint8_t* lds, const q
 // while the previous merge's read-back is still in flight; the pop's
 // bookkeeping (flags, pop count, the next unconsumed entry) then runs on the
 // merged beam.  Results and counters equal those of search_one.
-template <int D, int R, int LS, int NB>
+template <int D, int R, int LS, int NB, int LB>
 __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, const qgl::SearchLds& L,
                               const uint8_t* mlp) {
   using BV = BlockView<D, R>;
@@ -1265,7 +1277,7 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
       return;
     }
   }
-  int16_t* lut = reinterpret_cast<int16_t*>(lds + L.lut);
+  void* lut = lds + L.lut;
   uint64_t* sc = reinterpret_cast<uint64_t*>(lds + L.beam);    // merge output range (ef_cap words)
   uint64_t* cbuf = reinterpret_cast<uint64_t*>(lds + L.cand);  // candidates (R + 4 words)
   float* nkey = reinterpret_cast<float*>(lds + L.nkey);
@@ -1304,7 +1316,7 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
       return exact_dist<DPL>(qv, xv);
     }
   };
-  const float delta = build_lut<D, R>(a.qrot + q * D, lut, a.lut_pad);
+  const float delta = build_lut<D, R, LB>(a.qrot + q * D, lut, a.lut_pad);
 
   // the entry starts the beam, keyed by its exact distance; it is the first
   // vertex expanded, so its block serves both
@@ -1350,7 +1362,7 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
     uint32_t ns = vis.slot0(probe ? nb : 0u);
     uint32_t ne = vis.tab[ns];
     // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
-    const int S = b.fastscan(lut, lane, a.lut_pad);
+    const int S = b.template fastscan<LB>(lut, lane, a.lut_pad);
     // finish the pending merge: range slots still holding the sentinel take
     // the candidates in rank order
     if (pending) {
@@ -1639,13 +1651,13 @@ constexpr int waves_hint() {
 // For the narrow shapes the stop-only and mixed-batch kernels hold their
 // registers to 80, so that 6 wavefronts per SIMD fit (LDS sets residency for
 // the stop-only kernels anyway).
-template <int D, int R, bool GV, int LS, int NB>
+template <int D, int R, bool GV, int LS, int NB, int LB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_hint<D, R, LS, NB>()))) void search_kernel(
     SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
   const int lane = lane_id();
-  const qgl::SearchLds L = qgl::search_lds(D, R, a.ef_cap, GV ? 0 : (1 << a.hash_bits), a.k_cap);
+  const qgl::SearchLds L = qgl::search_lds(D, R, a.ef_cap, GV ? 0 : (1 << a.hash_bits), a.k_cap, LB);
   uint8_t* lds = smem + wave * L.total;
   uint8_t* mlp = smem + (blockDim.x >> 6) * L.total;  // after every wavefront's area
   if constexpr (mlp_in_lds<LS>) {
@@ -1664,9 +1676,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_hint<
     if (qi >= limit) break;
     const int64_t q = GV ? (int64_t)a.overflow_list[qi] : (int64_t)qi;
     if constexpr (NB > 0)
-      search_one_rb<D, R, LS, NB>(a, q, lds, L, mlp);
+      search_one_rb<D, R, LS, NB, LB>(a, q, lds, L, mlp);
     else
-      search_one<D, R, GV, LS>(a, q, lds, L, gbits, mlp);
+      search_one<D, R, GV, LS, LB>(a, q, lds, L, gbits, mlp);
   }
 }
 
@@ -1727,9 +1739,9 @@ hipError_t launch_encode(const float* X, const float* ROT, int64_t N, int D, con
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV, int LS, int NB>
+template <int D, int R, bool GV, int LS, int NB, int LB>
 static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t lds, hipStream_t st) {
-  auto kern = search_kernel<D, R, GV, LS, NB>;
+  auto kern = search_kernel<D, R, GV, LS, NB, LB>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1739,10 +1751,10 @@ static hipError_t launch_search_t(const SearchArgs& a, int grid, int wpb, size_t
   return hipGetLastError();
 }
 
-template <int D, int R, bool GV, int LS, int NB>
+template <int D, int R, bool GV, int LS, int NB, int LB>
 static int occupancy_t(int wpb, size_t lds) {
   int nb = 0;
-  auto kern = search_kernel<D, R, GV, LS, NB>;
+  auto kern = search_kernel<D, R, GV, LS, NB, LB>;
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -1755,47 +1767,58 @@ struct LaunchOp {
   int grid, wpb;
   size_t lds;
   hipStream_t st;
-  template <int D, int R, bool GV, int LS, int NB>
+  template <int D, int R, bool GV, int LS, int NB, int LB>
   hipError_t run() const {
-    return launch_search_t<D, R, GV, LS, NB>(*a, grid, wpb, lds, st);
+    return launch_search_t<D, R, GV, LS, NB, LB>(*a, grid, wpb, lds, st);
   }
 };
 
 struct OccupancyOp {
   int wpb;
   size_t lds;
-  template <int D, int R, bool GV, int LS, int NB>
+  template <int D, int R, bool GV, int LS, int NB, int LB>
   int run() const {
-    return occupancy_t<D, R, GV, LS, NB>(wpb, lds);
+    return occupancy_t<D, R, GV, LS, NB, LB>(wpb, lds);
   }
 };
 
-// The kernel instantiation for (D, R), pass, mode and beam storage.  Register
-// beams (nb 1, 2) exist for the main pass of the plain, stop-only and mixed
-// modes; the traced, "w/o ME" and overflow-pass kernels keep the beam in LDS.
+// The kernel instantiation for (D, R), pass, mode, beam storage and LUT
+// entry width.  Register beams (nb 1, 2) exist for the main pass of the
+// plain, stop-only and mixed modes; the traced, "w/o ME" and overflow-pass
+// kernels keep the beam in LDS.  The int32 LUT (lb 4) exists for the main
+// pass of the plain and mixed modes (the ones the autotuner times).
 template <int D, int R, class Op, class Ret>
-static Ret dispatch_mode(bool gv, int ls, int nb, const Op& op, Ret bad) {
+static Ret dispatch_mode(bool gv, int ls, int nb, int lb, const Op& op, Ret bad) {
   if (gv) {
+    if (lb != 2) return bad;
     switch (ls) {
-      case kLsOff: return op.template run<D, R, true, kLsOff, 0>();
-      case kLsStop: return op.template run<D, R, true, kLsStop, 0>();
-      case kLsTrace: return op.template run<D, R, true, kLsTrace, 0>();
-      case kMixed: return op.template run<D, R, true, kMixed, 0>();
-      case kMixedStop: return op.template run<D, R, true, kMixedStop, 0>();
-      case kNoMe: return op.template run<D, R, true, kNoMe, 0>();
+      case kLsOff: return op.template run<D, R, true, kLsOff, 0, 2>();
+      case kLsStop: return op.template run<D, R, true, kLsStop, 0, 2>();
+      case kLsTrace: return op.template run<D, R, true, kLsTrace, 0, 2>();
+      case kMixed: return op.template run<D, R, true, kMixed, 0, 2>();
+      case kMixedStop: return op.template run<D, R, true, kMixedStop, 0, 2>();
+      case kNoMe: return op.template run<D, R, true, kNoMe, 0, 2>();
       default: return bad;
     }
   }
-#define QG_NB(ls_)                                                                  \
-  (nb == 1 ? op.template run<D, R, false, ls_, 1>()                                 \
-           : nb == 2 ? op.template run<D, R, false, ls_, 2>() : op.template run<D, R, false, ls_, 0>())
+#define QG_NB(ls_, lb_)                                                                         \
+  (nb == 1 ? op.template run<D, R, false, ls_, 1, lb_>()                                        \
+           : nb == 2 ? op.template run<D, R, false, ls_, 2, lb_>() : op.template run<D, R, false, ls_, 0, lb_>())
+  if (lb == 4) {
+    switch (ls) {
+      case kLsOff: return QG_NB(kLsOff, 4);
+      case kMixed: return QG_NB(kMixed, 4);
+      default: return bad;
+    }
+  }
+  if (lb != 2) return bad;
   switch (ls) {
-    case kLsOff: return QG_NB(kLsOff);
-    case kLsStop: return QG_NB(kLsStop);
-    case kLsTrace: return op.template run<D, R, false, kLsTrace, 0>();
-    case kMixed: return QG_NB(kMixed);
-    case kMixedStop: return QG_NB(kMixedStop);
-    case kNoMe: return op.template run<D, R, false, kNoMe, 0>();
+    case kLsOff: return QG_NB(kLsOff, 2);
+    case kLsStop: return QG_NB(kLsStop, 2);
+    case kLsTrace: return op.template run<D, R, false, kLsTrace, 0, 2>();
+    case kMixed: return QG_NB(kMixed, 2);
+    case kMixedStop: return QG_NB(kMixedStop, 2);
+    case kNoMe: return op.template run<D, R, false, kNoMe, 0, 2>();
     default: return bad;
   }
 #undef QG_NB
@@ -1811,20 +1834,20 @@ int beam_regs(bool overflow_pass, int ls_mode, int ef_bound, int64_t n) {
   return (ef_bound <= 128 && (ls_mode == kLsOff || ls_mode == kMixed)) ? 2 : 0;
 }
 
-hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, int nb, const SearchArgs& a, int grid,
-                         int wpb, size_t lds, hipStream_t st) {
+hipError_t launch_search(int D, int R, bool overflow_pass, int ls_mode, int nb, int lb, const SearchArgs& a,
+                         int grid, int wpb, size_t lds, hipStream_t st) {
   const LaunchOp op{&a, grid, wpb, lds, st};
 #define QG_CASE(d, r) \
-  if (D == d && R == r) return dispatch_mode<d, r>(overflow_pass, ls_mode, nb, op, hipErrorInvalidValue);
+  if (D == d && R == r) return dispatch_mode<d, r>(overflow_pass, ls_mode, nb, lb, op, hipErrorInvalidValue);
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
   return hipErrorInvalidValue;
 }
 
-int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int nb, int wpb, size_t lds) {
+int search_occupancy(int D, int R, bool overflow_pass, int ls_mode, int nb, int lb, int wpb, size_t lds) {
   const OccupancyOp op{wpb, lds};
 #define QG_CASE(d, r) \
-  if (D == d && R == r) return dispatch_mode<d, r>(overflow_pass, ls_mode, nb, op, 0);
+  if (D == d && R == r) return dispatch_mode<d, r>(overflow_pass, ls_mode, nb, lb, op, 0);
   QG_SHAPES(QG_CASE)
 #undef QG_CASE
   return 0;

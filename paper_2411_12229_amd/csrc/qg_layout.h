@@ -44,10 +44,11 @@ __host__ __device__ constexpr int lut_rows_padded(int D, int R) { return D / 4 +
 // passes its features and first hidden layer.  The pieces
 // indexed by lane (LUT, candidates, beam) come first, at offsets fixed by D
 // and R, so one address register serves them with immediate offsets.
-__host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int hash_cap, int k_cap) {
+__host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int hash_cap, int k_cap,
+                                                int lut_entry_bytes = 2) {
   SearchLds s{};
   int o = 0;
-  s.lut = o;   o += align16(lut_rows_padded(D, R) * 32);
+  s.lut = o;   o += align16(lut_rows_padded(D, R) * 16 * lut_entry_bytes);
   s.cand = o;  o += 8 * (R + 4);
   s.beam = o;  o += 8 * ef_cap;
   s.hash = o;  o += 4 * hash_cap;

@@ -149,7 +149,7 @@ class Index:
         """Pick the launch shape (wavefronts per workgroup, visited-hash factor, cap on resident
         wavefronts per compute unit, beam storage, LUT layout) by timing searches of these queries; returns
         (wpb, hash_factor, cu_waves (0 = no cap), best ms per call, beam (1 = registers, 0 = LDS),
-        lut (1 = padded rows, 0 = packed))."""
+        lut (bit 0: padded rows, bit 1: int32 entries))."""
         w, h, c, b, lu = (ctypes.c_int32() for _ in range(5))
         ms = ctypes.c_double()
         _check(_lib.qg_autotune(self._h, _dev(queries, torch.float32, "queries"), queries.shape[0], k, ef, flags,

@@ -206,7 +206,7 @@ def test_autotune_keeps_results(cfg1, k, ef):
     print(f"autotune k={k} ef={ef}: wpb={wpb} hash factor={hf} cu waves={cw} beam={beam} lut={lut} {ms:.3f} ms",
           flush=True)
     assert wpb in (1, 2, 4, 8) and hf in (2, 3, 4) and cw in (0, 16, 20, 24) and beam in (0, 1) and ms > 0
-    assert lut in (0, 1)
+    assert lut in (0, 1, 2, 3)
     assert ef <= 128 or beam == 1  # larger beams are always in LDS; nothing to choose
     after = idx.search(Qd, k, ef, stats=True)
     torch.cuda.synchronize()
@@ -215,13 +215,13 @@ def test_autotune_keeps_results(cfg1, k, ef):
     oi, od = oracle.search(c["blocks"], 128, 32, c["e"], c["M"], c["Q"], k, ef)
     assert np.array_equal(after[0].cpu().numpy(), oi) and np.array_equal(after[1].cpu().numpy(), od)
     # a shape set by hand: two wavefronts per workgroup, F = 4, at most 16 resident per compute unit
-    for beam_hand, lut_hand in ((0, 1), (1, 0), (0, 0)):
+    for beam_hand, lut_hand in ((0, 1), (1, 0), (0, 0), (1, 3), (0, 2), (1, 2)):
         idx.set_launch(2, 4, 16, beam_hand, lut_hand)
         hand = idx.search(Qd, k, ef, stats=True)
         torch.cuda.synchronize()
         for a, b in zip(before, hand):
             assert torch.equal(a, b)
-    for bad in ((3, 3, 0, 1), (4, 5, 0, 1), (4, 3, -1, 1), (4, 3, 65, 1), (4, 3, 0, 2), (4, 3, 0, 1, 2)):
+    for bad in ((3, 3, 0, 1), (4, 5, 0, 1), (4, 3, -1, 1), (4, 3, 65, 1), (4, 3, 0, 2), (4, 3, 0, 1, 4), (4, 3, 0, 1, -1)):
         with pytest.raises(qg.QGError):
             idx.set_launch(*bad)
     idx.set_launch(wpb, hf, cw, beam, lut)

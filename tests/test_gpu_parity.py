@@ -163,17 +163,26 @@ def test_search_parity_shapes(D, R, cfg):
         gpu = _search(idx, Q, k, ef)
         orc = oracle.search(blocks, D, R, e, M, Q, k, ef, with_stats=True)
         _assert_same(gpu, orc, f"D={D} R={R} k={k} ef={ef}")
+        # every LUT layout (bit 0: padded rows, bit 1: int32 entries) gives the same search
+        for lut in (0, 2, 3):
+            idx.set_launch(4, 3, 0, 1, lut)
+            _assert_same(_search(idx, Q, k, ef), orc, f"D={D} R={R} k={k} ef={ef} LUT layout {lut}")
+        idx.set_launch(4, 3, 0, 1, 1)
     # the per-query (mixed batch) kernel on the same shape
     ks = np.resize(np.array([10, 100, 1], np.int32), len(Q))
     efs = np.resize(np.array([32, 128, 64], np.int32), len(Q))
-    mi, md, ms = idx.search_mixed(T(Q), T(ks), T(efs), 100, 128, stats=True)
-    torch.cuda.synchronize()
-    mi, md, ms = mi.cpu().numpy(), md.cpu().numpy(), ms.cpu().numpy()
-    for k, ef in ((10, 32), (100, 128), (1, 64)):
-        sel = np.nonzero((ks == k) & (efs == ef))[0]
-        oi, od, os_ = oracle.search(blocks, D, R, e, M, Q[sel], k, ef, with_stats=True)
-        _assert_same((mi[sel, :k], md[sel, :k], ms[sel]), (oi, od, os_), f"mixed D={D} R={R} k={k} ef={ef}")
-        assert (mi[sel, k:] == -1).all()
+    for lut in (1, 3):  # int16 and int32 entries
+        idx.set_launch(4, 3, 0, 1, lut)
+        mi, md, ms = idx.search_mixed(T(Q), T(ks), T(efs), 100, 128, stats=True)
+        torch.cuda.synchronize()
+        mi, md, ms = mi.cpu().numpy(), md.cpu().numpy(), ms.cpu().numpy()
+        for k, ef in ((10, 32), (100, 128), (1, 64)):
+            sel = np.nonzero((ks == k) & (efs == ef))[0]
+            oi, od, os_ = oracle.search(blocks, D, R, e, M, Q[sel], k, ef, with_stats=True)
+            _assert_same((mi[sel, :k], md[sel, :k], ms[sel]), (oi, od, os_),
+                         f"mixed D={D} R={R} k={k} ef={ef} LUT layout {lut}")
+            assert (mi[sel, k:] == -1).all()
+    idx.set_launch(4, 3, 0, 1, 1)
     # the learned-stop kernel (MLP in LDS) on the same shape, theta set so that some queries stop
     rng = np.random.default_rng(D + R)
     w = ((rng.standard_normal(oracle.LS_PARAMS) * 0.3).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
