@@ -75,18 +75,26 @@ def make_graph(c, X, M, entry, dev, kind, build_ef=400, build_iters=3):
 
 
 def serve_trace(qg, idx, Q, qsel, ks, efs, arrival, ef_max, stop=None, with_ids=False, streams=3,
-                max_batch=8192):
+                max_batch=8192, targets=None, recall_map=None):
     """Replay one open-loop trace through the library's serving loop.  Returns (row, tags, ids or None): the
     row holds the completed rate, p50/p99 latency and where the slowest 1% of requests spent their time,
     from the server's batch records (queue wait before their batch was taken, host enqueue, device time
-    between the batch's events, and the rest until the worker saw completion)."""
+    between the batch's events, and the rest until the worker saw completion).  With targets (a recall
+    target per request) and recall_map ({(k, target): ef}) the requests name targets and the server maps
+    them to beams (efs must then be that mapping, for the analysis)."""
     srv = qg.Server(idx, streams=streams, max_batch=max_batch, k_max=int(ks.max()), ef_max=ef_max)
     try:
         if stop is not None:
             srv.set_stop(*stop)
+        if recall_map is not None:
+            rows = list(recall_map.items())
+            srv.set_recall_map([k for (k, _), _ in rows], [t for (_, t), _ in rows], [e for _, e in rows])
         # latencies are taken by the server when each batch completes; results are collected after the trace
         t0 = time.perf_counter()
-        srv.replay(Q[qsel], ks, efs, arrival)
+        if targets is not None:
+            srv.replay_target(Q[qsel], ks, targets, arrival)
+        else:
+            srv.replay(Q[qsel], ks, efs, arrival)
         srv.drain()
         wall = time.perf_counter() - t0
         parts, got = [], 0
@@ -944,7 +952,8 @@ def serve_leg(args, dev):
         arrival = np.cumsum(rng.exponential(1.0 / rate, n))
         stop = (bits, theta, t_min, t_every) if with_stop else None
         res, tags, ids = serve_trace(qg, idx, Q, qsel, ks, efs, arrival, ef_max, stop=stop, with_ids=True,
-                                     streams=args.serve_streams)
+                                     streams=args.serve_streams, targets=np.array(targets, np.float32)[tg],
+                                     recall_map=ef_map)
         per_class = []
         for k in ks_all:
             for ti, target in enumerate(targets):

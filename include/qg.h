@@ -291,6 +291,25 @@ int qg_server_set_stop(qg_server *s, const qg_stop_params *stop);
  * the results.  Thread-safe; never blocks on the device. */
 int qg_server_submit(qg_server *s, const float *query, int32_t k, int32_t ef, uint64_t tag);
 
+/* Beam sizes for target recalls (requests may name a recall@k target instead
+ * of a beam): n rows of (k[i], target[i], ef[i]) host arrays, e.g. calibrated
+ * on held-out queries.  A request with (k, target) takes the ef of the row
+ * with the same k and the smallest target not below its own.  Replaces any
+ * earlier map; call it while no request waits or runs.  QG_EINVAL for a k or
+ * ef outside the server's bounds or a target outside (0, 1].  (Serving
+ * plumbing; the paper's search takes a beam size.) */
+int qg_server_set_recall_map(qg_server *s, const int32_t *k, const float *target, const int32_t *ef, int32_t n);
+
+/* qg_server_submit with a target recall in place of ef, looked up in the
+ * recall map (QG_EINVAL when no row covers (k, target)). */
+int qg_server_submit_target(qg_server *s, const float *query, int32_t k, float target, uint64_t tag);
+
+/* qg_server_replay with a target recall per request (target[n], host) in place
+ * of ef; every (k, target) must be covered by the recall map (checked before
+ * the replay starts). */
+int qg_server_replay_target(qg_server *s, const float *queries, const int32_t *k, const float *target,
+                            const double *arrival_s, int64_t n);
+
 /* Move up to max_results finished requests out of the server, oldest first.
  * Host outputs, each nullable: tags[n], ids[n][k_max] and dists[n][k_max]
  * (a request's k results, then (-1, +inf)), latency_s[n] (submission, or

@@ -115,6 +115,13 @@ struct qg_server {
   bool use_stop = false;         // batches run with the learned stop (qg_server_set_stop)
   qg_stop_params stop_params{};
   int64_t submitted = 0, completed = 0, batches = 0, largest = 0;
+  struct RecallRow {
+    int32_t k;
+    float target;
+    int32_t ef;
+  };
+  std::vector<RecallRow> recall_map;     // sorted by (k, target)
+  std::vector<int32_t> replay_ef;        // the beams of a replay given by target recalls
   static constexpr size_t kMaxRecords = size_t(1) << 22;  // batch records kept (the first 4M)
   std::vector<qg_server_batch> records;
   int error = QG_OK;
@@ -447,6 +454,65 @@ int qg_server_submit(qg_server* sv, const float* query, int32_t k, int32_t ef, u
   }
   sv->cv.notify_one();
   return QG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// The beam of (k, target) from the recall map, or 0 when no row covers it
+// (called with the server's lock held or before its threads read the map).
+int32_t beam_for(const qg_server* sv, int32_t k, float target) {
+  for (const auto& r : sv->recall_map)
+    if (r.k == k && r.target >= target) return r.ef;
+  return 0;
+}
+}  // namespace
+
+extern "C" {
+
+int qg_server_set_recall_map(qg_server* sv, const int32_t* k, const float* target, const int32_t* ef, int32_t n) {
+  if (!sv || n < 0 || (n > 0 && (!k || !target || !ef))) return qgi::set_error(QG_EINVAL, "bad recall map arguments");
+  std::vector<qg_server::RecallRow> rows;
+  for (int32_t i = 0; i < n; ++i) {
+    if (k[i] < 1 || k[i] > sv->k_max || ef[i] < 1 || ef[i] > sv->ef_max || !(target[i] > 0.0f && target[i] <= 1.0f))
+      return qgi::set_error(QG_EINVAL, "recall map row outside the server's bounds");
+    rows.push_back({k[i], target[i], ef[i]});
+  }
+  std::sort(rows.begin(), rows.end(), [](const qg_server::RecallRow& a, const qg_server::RecallRow& b) {
+    return a.k < b.k || (a.k == b.k && a.target < b.target);
+  });
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->npending > 0 || sv->completed < sv->submitted)
+    return qgi::set_error(QG_EINVAL, "requests are waiting or in flight");
+  sv->recall_map = std::move(rows);
+  return QG_OK;
+}
+
+int qg_server_submit_target(qg_server* sv, const float* query, int32_t k, float target, uint64_t tag) {
+  if (!sv) return qgi::set_error(QG_EINVAL, "server is NULL");
+  int32_t ef;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    ef = beam_for(sv, k, target);
+  }
+  if (ef == 0) return qgi::set_error(QG_EINVAL, "no recall map row covers this k and target");
+  return qg_server_submit(sv, query, k, ef, tag);
+}
+
+int qg_server_replay_target(qg_server* sv, const float* queries, const int32_t* k, const float* target,
+                            const double* arrival_s, int64_t n) {
+  if (!sv || n < 0 || (n > 0 && (!queries || !k || !target || !arrival_s)))
+    return qgi::set_error(QG_EINVAL, "bad replay arguments");
+  if (sv->producer.joinable()) return qgi::set_error(QG_EINVAL, "a replay is already running");
+  std::vector<int32_t> ef((size_t)n);
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (int64_t i = 0; i < n; ++i)
+      if ((ef[(size_t)i] = beam_for(sv, k[i], target[i])) == 0)
+        return qgi::set_error(QG_EINVAL, "no recall map row covers a request's k and target");
+  }
+  sv->replay_ef = std::move(ef);  // read by the replay thread until the replay ends
+  return qg_server_replay(sv, queries, k, sv->replay_ef.data(), arrival_s, n);
 }
 
 int64_t qg_server_poll(qg_server* sv, int64_t max_results, uint64_t* tags, int32_t* ids, float* dists,

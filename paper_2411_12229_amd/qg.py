@@ -84,6 +84,9 @@ def _load():
         "qg_server_poll": ([P, i64, P, P, P, P, P], i64),
         "qg_server_batches": ([P, i64, i64, P], i64),
         "qg_server_replay": ([P, P, P, P, P, i64], c_int),
+        "qg_server_set_recall_map": ([P, P, P, P, i32], c_int),
+        "qg_server_submit_target": ([P, P, i32, ctypes.c_float, ctypes.c_uint64], c_int),
+        "qg_server_replay_target": ([P, P, P, P, P, i64], c_int),
         "qg_server_set_stop": ([P, ctypes.POINTER(StopParams)], c_int),
         "qg_server_drain": ([P, ctypes.c_double], c_int),
         "qg_server_stats": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
@@ -472,6 +475,36 @@ class Server:
         if q.shape[0] != self.d:
             raise ValueError("query has the wrong dimension")
         _check(_lib.qg_server_submit(self._h, ctypes.c_void_p(q.ctypes.data), k, ef, ctypes.c_uint64(tag)))
+
+    def set_recall_map(self, k, target, ef) -> None:
+        """Beam per (k, target recall): rows of equal-length sequences k, target, ef."""
+        ka = np.ascontiguousarray(k, dtype=np.int32)
+        ta = np.ascontiguousarray(target, dtype=np.float32)
+        ea = np.ascontiguousarray(ef, dtype=np.int32)
+        if not (ka.shape == ta.shape == ea.shape) or ka.ndim != 1:
+            raise ValueError("recall map rows must be equal-length vectors")
+        _check(_lib.qg_server_set_recall_map(self._h, _host(ka, np.int32, "k"), _host(ta, np.float32, "target"),
+                                             _host(ea, np.int32, "ef"), int(ka.shape[0])))
+
+    def submit_target(self, query: np.ndarray, k: int, target: float, tag: int) -> None:
+        """submit with a target recall, mapped to a beam by the recall map."""
+        q = np.ascontiguousarray(query, dtype=np.float32).reshape(-1)
+        if q.shape[0] != self.d:
+            raise ValueError("query has the wrong dimension")
+        _check(_lib.qg_server_submit_target(self._h, ctypes.c_void_p(q.ctypes.data), k, float(target),
+                                            ctypes.c_uint64(tag)))
+
+    def replay_target(self, queries: np.ndarray, k: np.ndarray, target: np.ndarray, arrival_s: np.ndarray) -> None:
+        """replay with a target recall per request in place of ef (mapped by the recall map)."""
+        arrs = (np.ascontiguousarray(queries, dtype=np.float32), np.ascontiguousarray(k, dtype=np.int32),
+                np.ascontiguousarray(target, dtype=np.float32), np.ascontiguousarray(arrival_s, dtype=np.float64))
+        n = arrs[0].shape[0]
+        if arrs[0].shape != (n, self.d) or arrs[1].shape != (n,) or arrs[2].shape != (n,) or arrs[3].shape != (n,):
+            raise ValueError("trace shape mismatch")
+        _check(_lib.qg_server_replay_target(self._h, _host(arrs[0], np.float32, "queries"),
+                                            _host(arrs[1], np.int32, "k"), _host(arrs[2], np.float32, "target"),
+                                            _host(arrs[3], np.float64, "arrival_s"), n))
+        self._traces.append(arrs)  # accepted: kept alive until a drain succeeds or close()
 
     def poll(self, max_results: int = 1 << 16, payload: bool = True, with_batch: bool = False):
         """-> (tags uint64 [n], ids int32 [n,k_max], dists f32 [n,k_max], latency s [n][, batch index int64 [n]])

@@ -211,3 +211,47 @@ def test_trace_outlives_a_timed_out_drain(cfg1):
     assert sorted(tags.tolist()) == list(range(n))
     gi, gd = c["idx"].search(T(c["Q"][sel[tags]]), 10, 256)
     assert np.array_equal(ids, gi.cpu().numpy()) and np.array_equal(dists, gd.cpu().numpy())
+
+
+def test_target_recall_requests(cfg1):
+    """Requests that name a recall target take the beam the recall map gives
+    their (k, target); each result equals that query searched alone with it,
+    for submitted and for replayed requests.  Unmapped (k, target) pairs are
+    refused."""
+    c = cfg1
+    rng = np.random.default_rng(44)
+    n = 300
+    sel = rng.integers(0, len(c["Q"]), n)
+    ks = rng.choice([1, 10], n).astype(np.int32)
+    tg = rng.choice([0.9, 0.95, 0.99], n).astype(np.float32)
+    emap = {(1, 0.9): 16, (1, 0.95): 32, (1, 0.99): 64, (10, 0.9): 24, (10, 0.95): 48, (10, 0.99): 96}
+    efs = np.array([emap[(int(k), round(float(t), 2))] for k, t in zip(ks, tg)], np.int32)
+    srv = qg.Server(c["idx"], streams=2, max_batch=128, k_max=10, ef_max=96)
+    try:
+        rows = list(emap.items())
+        srv.set_recall_map([kk for (kk, _), _ in rows], [t for (_, t), _ in rows], [e for _, e in rows])
+        with pytest.raises(qg.QGError):  # no row for k = 5
+            srv.submit_target(c["Q"][0], 5, 0.9, 0)
+        with pytest.raises(qg.QGError):  # no target above 0.99
+            srv.submit_target(c["Q"][0], 10, 0.999, 0)
+        with pytest.raises(qg.QGError):  # a beam above the server's bound
+            srv.set_recall_map([10], [0.9], [97])
+        for i in range(n):
+            srv.submit_target(c["Q"][sel[i]], int(ks[i]), float(tg[i]), i)
+        srv.drain()
+        got_s = _collect(srv, n)
+        srv.replay_target(c["Q"][sel], ks, tg, np.linspace(0.0, 0.005, n))
+        srv.drain()
+        got_r = _collect(srv, n)
+    finally:
+        srv.close()
+    for tags, ids, dists, _ in (got_s, got_r):
+        tags = tags.astype(np.int64)
+        assert sorted(tags.tolist()) == list(range(n))
+        for (k, t), e in emap.items():
+            rows_ = np.nonzero((ks[tags] == k) & (efs[tags] == e))[0]
+            if rows_.size == 0:
+                continue
+            gi, gd = c["idx"].search(T(c["Q"][sel[tags[rows_]]]), k, e)
+            assert np.array_equal(ids[rows_, :k], gi.cpu().numpy())
+            assert np.array_equal(dists[rows_, :k], gd.cpu().numpy())
