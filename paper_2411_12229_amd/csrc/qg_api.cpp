@@ -575,6 +575,8 @@ static int search_impl(const qg_index* cidx, const float* queries, int64_t nq, i
   const int lb = (idx->lut32 && (ls == 0 || ls == 3)) ? 4 : 2;
   const qgl::SearchLds L = qgl::search_lds(idx->D, idx->R, ef_cap, 1 << hbits, k_cap, lb);
   const qgl::SearchLds Lf = qgl::search_lds(idx->D, idx->R, ef_cap, 0, k_cap);
+  if (L.hash % 16 || L.total % 16)  // the kernels read the hash 16 bytes at a time
+    return fail(QG_EUNSUPPORTED, "per-query LDS layout is not 16-byte aligned");
   const size_t lds_cap = 160 * 1024;
   const bool mlp_lds = ls == 1 || ls == 4;
   const size_t extra = mlp_lds ? qgk::mlp_lds_bytes() : 0;  // MLP image shared by a workgroup

@@ -485,10 +485,25 @@ struct Visited {
   int hbits;
   uint32_t* bits;
 
+  // First slot of id's probe sequence: a multiplicative hash.
   __device__ __forceinline__ uint32_t slot0(uint32_t id) const {
     return (id * 0x9E3779B1u) >> (32 - hbits);
   }
+  // The register-beam search starts every probe sequence at a multiple of 4
+  // instead, so that a probe tests four slots with one 16-byte LDS read (the
+  // table is 16-byte aligned).  An id sits before the first empty slot of its
+  // sequence (ids are never removed), so a probe ends at the first group of
+  // four that holds the id or an empty slot.  (The LDS-beam search probes one
+  // slot at a time per lane, where the wider read measured slower.)
+  __device__ __forceinline__ uint32_t slot4(uint32_t id) const { return slot0(id) & ~3u; }
+  __device__ __forceinline__ uint4 group(uint32_t slot) const { return *reinterpret_cast<const uint4*>(tab + slot); }
 };
+__device__ __forceinline__ bool group_has(const uint4& w, uint32_t id) {
+  return min(min(w.x ^ id, w.y ^ id), min(w.z ^ id, w.w ^ id)) == 0u;
+}
+__device__ __forceinline__ bool group_full(const uint4& w) {  // no empty slot (ids are below kEmpty)
+  return max(max(w.x, w.y), max(w.z, w.w)) != kEmpty;
+}
 
 // Membership test.  For the LDS hash, end receives the slot where the probe
 // stopped: when id is absent, the first empty slot of its probe sequence,
@@ -542,9 +557,9 @@ __device__ __forceinline__ bool visited_insert(const Visited& v, uint32_t id, in
 }
 
 // Insert id (wave-uniform), known to be absent, into the LDS hash: the first
-// empty slot of its probe sequence, found by one read of 64 consecutive slots.
-__device__ __forceinline__ void visited_add_absent(const Visited& v, uint32_t id, int lane) {
-  uint32_t base = v.slot0(id);
+// empty slot of its probe sequence (which starts at `base`), found by reads of
+// 64 consecutive slots.
+__device__ __forceinline__ void visited_add_absent(const Visited& v, uint32_t id, uint32_t base, int lane) {
   for (;;) {
     const uint32_t s = (base + lane) & v.mask;
     const uint64_t em = ballot(v.tab[s] == kEmpty);
@@ -1353,14 +1368,14 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
       }
     }
     // visited probes: p's insertion run (64 consecutive slots) and each
-    // neighbour's first slot (p itself is excluded explicitly: it is inserted
-    // below, after these reads)
-    const uint32_t pslot = vis.slot0(p);
+    // neighbour's first group of four slots (p itself is excluded explicitly:
+    // it is inserted below, after these reads)
+    const uint32_t pslot = vis.slot4(p);
     const uint32_t prun = vis.tab[(pslot + lane) & vis.mask];
     const uint32_t nb = (uint32_t)b.nb;
     const bool probe = (lane % LPN == 0) && b.nb >= 0 && nb != p;
-    uint32_t ns = vis.slot0(probe ? nb : 0u);
-    uint32_t ne = vis.tab[ns];
+    uint32_t ns = vis.slot4(probe ? nb : 0u);
+    uint4 ne = vis.group(ns);
     // FastScan estimates of all neighbours (Eq. normalization with Eq. 3.1)
     const int S = b.template fastscan<LB>(lut, lane, a.lut_pad);
     // finish the pending merge: range slots still holding the sentinel take
@@ -1435,7 +1450,7 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
       if (em) {
         if (lane == first_lane(em)) vis.tab[(pslot + lane) & vis.mask] = p;
       } else {
-        visited_add_absent(vis, p, lane);  // 64 occupied slots in a row (the table is at most half full)
+        visited_add_absent(vis, p, pslot, lane);  // 64 occupied slots in a row (the table is at most half full)
       }
     }
     if (++nvis > vis_limit) {  // on-chip visited set full: hand the query to the overflow path
@@ -1447,15 +1462,16 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
     }
     ++expansions;
 
-    // visited filter: continue the probes that met another id
-    bool seen = probe && ne == nb;
-    bool more = probe && ne != nb && ne != kEmpty;
+    // visited filter: the probes that met four other ids go on to the next
+    // group
+    bool seen = probe && group_has(ne, nb);
+    bool more = probe && !seen && group_full(ne);
     while (ballot(more)) {
       if (more) {
-        ns = (ns + 1) & vis.mask;
-        ne = vis.tab[ns];
-        seen = ne == nb;
-        more = ne != nb && ne != kEmpty;
+        ns = (ns + 4) & vis.mask;
+        ne = vis.group(ns);
+        seen = group_has(ne, nb);
+        more = !seen && group_full(ne);
       }
     }
     bool valid = probe && !seen;
@@ -1464,10 +1480,8 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
     if (size == ef) valid = valid && cand < tail;  // would fall past the cut anyway
     const uint64_t V = ballot(valid);
     const int nv = uni((int)__popcll(V));
-    if (nv > 0) {  // compacted for the merge's broadcast reads (after the read-back above: LDS keeps order)
-      if (valid) cbuf[lanes_below(V)] = cand;
-      if (lane < 4) cbuf[nv + lane] = kNone;  // padding: below no entry, no candidate
-    }
+    if (nv > 0 && valid) cbuf[lanes_below(V)] = cand;  // compacted for the merge's broadcast reads (after
+                                                         // the read-back above: LDS keeps order)
 
     // best candidate (the smallest (estimate, id) among them)
     uint64_t best = kNone;
@@ -1561,16 +1575,20 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
         cnt[r] = 0;
       }
       int rank = 0;
-      const int nv4 = (nv + 3) & ~3;
-      for (int t = 0; t < nv4; t += 4) {
+      auto count = [&](uint64_t ct) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const uint64_t ct = cbuf[t + u];
-#pragma unroll
-          for (int r = 0; r < NB; ++r) cnt[r] += ct < bm[r];
-          rank += ct < cand;
-        }
+        for (int r = 0; r < NB; ++r) cnt[r] += ct < bm[r];
+        rank += ct < cand;
+      };
+      int t = 0;
+      for (; t + 4 <= nv; t += 4) {  // four broadcast reads in flight
+        const uint64_t c0 = cbuf[t], c1 = cbuf[t + 1], c2 = cbuf[t + 2], c3 = cbuf[t + 3];
+        count(c0);
+        count(c1);
+        count(c2);
+        count(c3);
       }
+      for (; t < nv; ++t) count(cbuf[t]);  // the last one to three
       const int nsz = (size + nv < ef) ? size + nv : ef;
 #pragma unroll
       for (int r = 0; r < NB; ++r)
@@ -1643,7 +1661,8 @@ constexpr int waves_hint() {
   return D > 256 || NB > 0 ? 1 : (mlp_in_lds<LS> || LS == kMixed) ? 6 : 1;
 }
 
-// Each wavefront takes queries from a shared counter until none is left.
+// Each wavefront takes queries until none is left: first its own index, then
+// from a shared counter.
 // GV = false: main pass over all queries with the LDS visited hash.
 // GV = true : overflow pass over the queries the main pass handed over, with
 //             a global bitset per wavefront.
@@ -1669,16 +1688,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_hint<
   int* ctr = a.counters + (GV ? 2 : 0);
   const int64_t limit = GV ? (int64_t)__hip_atomic_load(a.counters + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                            : a.nq;
-  for (;;) {
-    int qi = 0;
-    if (lane == 0) qi = atomicAdd(ctr, 1);
-    qi = __builtin_amdgcn_readlane(qi, 0);
-    if (qi >= limit) break;
-    const int64_t q = GV ? (int64_t)a.overflow_list[qi] : (int64_t)qi;
+  // A wavefront's first query is its own index; the later ones come from the
+  // shared counter, offset by the number of wavefronts.  (A device-wide atomic
+  // on one address is served one at a time, so taking every first query from
+  // it would start the wavefronts only gradually.)
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t qi = wid; qi < limit;) {
+    const int64_t q = GV ? (int64_t)a.overflow_list[qi] : qi;
     if constexpr (NB > 0)
       search_one_rb<D, R, LS, NB, LB>(a, q, lds, L, mlp);
     else
       search_one<D, R, GV, LS, LB>(a, q, lds, L, gbits, mlp);
+    int c = 0;
+    if (lane == 0) c = atomicAdd(ctr, 1);
+    qi = nwaves + __builtin_amdgcn_readlane(c, 0);
   }
 }
 

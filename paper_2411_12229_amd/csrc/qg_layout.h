@@ -43,7 +43,10 @@ __host__ __device__ constexpr int lut_rows_padded(int D, int R) { return D / 4 +
 // query when D > 256; aux: 256 bytes through which the learned stop's MLP
 // passes its features and first hidden layer.  The pieces
 // indexed by lane (LUT, candidates, beam) come first, at offsets fixed by D
-// and R, so one address register serves them with immediate offsets.
+// and R, so one address register serves them with immediate offsets.  With R
+// even, D and the caps multiples of 4 (the host rounds them), the hash and the
+// whole area are multiples of 16 bytes, so the hash can be read 16 bytes at a
+// time in every wavefront's area.
 __host__ __device__ inline SearchLds search_lds(int D, int R, int ef_cap, int hash_cap, int k_cap,
                                                 int lut_entry_bytes = 2) {
   SearchLds s{};
