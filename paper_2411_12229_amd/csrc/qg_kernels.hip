@@ -188,7 +188,13 @@ __device__ __forceinline__ float exact_dist(const float (&qv)[DPL], const float 
 // out[r][i] = fl32(sum_j M[i][j] in[r][j]), fp64 products accumulated over j
 // ascending (each 16x16x4 MFMA applies its four k terms in order as fused
 // multiply-adds onto the accumulator), one 16x16 output tile per wavefront.
-// Block (0,0) also clears `nzero` ints at `zero` for the kernels that follow.
+// Workgroup b takes row group 8 (b / 8 / T) + b % 8 and column tile
+// (b / 8) % T (T = D / 16): workgroups are dealt to the 8 XCDs round robin, so
+// the T tiles of one group of 16 rows run on one XCD and read those rows
+// through its L2 once.  Workgroup 0 also clears `nzero` ints at `zero` for the
+// kernels that follow.  V4: the input rows start 16-byte aligned, so each lane
+// moves four columns per load and per LDS store.
+template <bool V4>
 __global__ __launch_bounds__(64) void rotate_kernel(const float* __restrict__ in, int64_t n, int D,
                                                     const float* __restrict__ M, float* __restrict__ out,
                                                     int* __restrict__ zero, int nzero) {
@@ -196,31 +202,60 @@ __global__ __launch_bounds__(64) void rotate_kernel(const float* __restrict__ in
   // through LDS with coalesced loads (rows padded to 68 floats); the next
   // chunk's loads are issued before this chunk's products
   constexpr int KC = 64, LD = KC + 4;
-  __shared__ float As[16 * LD], Bs[16 * LD];
+  __shared__ __align__(16) float As[16 * LD];
+  __shared__ __align__(16) float Bs[16 * LD];
   const int lane = threadIdx.x;
-  if (zero && blockIdx.x == 0 && blockIdx.y == 0 && lane < nzero) zero[lane] = 0;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
-  const int i0 = blockIdx.y * 16;
+  if (zero && blockIdx.x == 0 && lane < nzero) zero[lane] = 0;
+  const int T = D / 16;
+  const int64_t rest = blockIdx.x >> 3;
+  const int64_t r0 = ((rest / T) * 8 + (blockIdx.x & 7)) * 16;
+  const int i0 = (int)(rest % T) * 16;
+  if (r0 >= n) return;  // the grid's padding to a multiple of 8 row groups (or an empty batch)
   const int rl = lane & 15, kk = lane >> 4;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
+  // V4: lane l moves columns 4 (l % 16) .. + 3 of rows l / 16 + 4 t (t < 4);
+  // otherwise column l of every row.  Columns past kw (a multiple of 16)
+  // re-read the last valid ones into the unread part of the row.
   float va[16], vb[16];
-  auto load = [&](int k0) {
-    const int kw = D - k0 < KC ? D - k0 : KC;  // a multiple of 16
-    const int c = min(lane, kw - 1);  // columns past kw re-read column kw - 1 into the unread part of the row
+  auto load = [&](int k0) __attribute__((always_inline)) {
+    const int kw = D - k0 < KC ? D - k0 : KC;
+    if constexpr (V4) {
+      const int c = min(4 * (lane & 15), kw - 4);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t ra = r0 + r < n ? r0 + r : 0;  // rows past n only feed outputs that are not stored
-      va[r] = in[ra * D + k0 + c];
-      vb[r] = M[(int64_t)(i0 + r) * D + k0 + c];
+      for (int t = 0; t < 4; ++t) {
+        const int r = 4 * t + (lane >> 4);
+        const int64_t ra = r0 + r < n ? r0 + r : 0;  // rows past n only feed outputs that are not stored
+        const float4 x = *reinterpret_cast<const float4*>(in + ra * D + k0 + c);
+        const float4 y = *reinterpret_cast<const float4*>(M + (int64_t)(i0 + r) * D + k0 + c);
+        va[4 * t] = x.x, va[4 * t + 1] = x.y, va[4 * t + 2] = x.z, va[4 * t + 3] = x.w;
+        vb[4 * t] = y.x, vb[4 * t + 1] = y.y, vb[4 * t + 2] = y.z, vb[4 * t + 3] = y.w;
+      }
+    } else {
+      const int c = min(lane, kw - 1);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t ra = r0 + r < n ? r0 + r : 0;
+        va[r] = in[ra * D + k0 + c];
+        vb[r] = M[(int64_t)(i0 + r) * D + k0 + c];
+      }
     }
   };
   load(0);
   for (int k0 = 0; k0 < D; k0 += KC) {
     const int kw = D - k0 < KC ? D - k0 : KC;
+    if constexpr (V4) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      As[r * LD + lane] = va[r];
-      Bs[r * LD + lane] = vb[r];
+      for (int t = 0; t < 4; ++t) {
+        const int o = (4 * t + (lane >> 4)) * LD + 4 * (lane & 15);
+        *reinterpret_cast<float4*>(&As[o]) = make_float4(va[4 * t], va[4 * t + 1], va[4 * t + 2], va[4 * t + 3]);
+        *reinterpret_cast<float4*>(&Bs[o]) = make_float4(vb[4 * t], vb[4 * t + 1], vb[4 * t + 2], vb[4 * t + 3]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        As[r * LD + lane] = va[r];
+        Bs[r * LD + lane] = vb[r];
+      }
     }
     __syncthreads();
     if (k0 + KC < D) load(k0 + KC);
@@ -1746,11 +1781,17 @@ bool shape_supported(int D, int R) {
 hipError_t launch_rotate(const float* in, int64_t n, int D, const float* M, float* out, int* zero, int nzero,
                          hipStream_t st) {
   if (n <= 0) {
-    if (zero && nzero > 0) hipLaunchKernelGGL(rotate_kernel, dim3(1, 1), dim3(64), 0, st, in, 0, D, M, out, zero, nzero);
+    if (zero && nzero > 0)
+      hipLaunchKernelGGL(rotate_kernel<false>, dim3(1), dim3(64), 0, st, in, 0, D, M, out, zero, nzero);
     return hipGetLastError();
   }
-  dim3 grid((unsigned)((n + 15) / 16), (unsigned)(D / 16));
-  hipLaunchKernelGGL(rotate_kernel, grid, dim3(64), 0, st, in, n, D, M, out, zero, nzero);
+  const int64_t groups = (n + 15) / 16;  // of 16 rows, padded to a multiple of 8 (one per XCD)
+  const dim3 grid((unsigned)(((groups + 7) / 8) * 8 * (D / 16)));
+  // four columns per lane when every row starts 16-byte aligned (M is the library's own allocation)
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(M)) % 16 == 0 && D % 4 == 0)
+    hipLaunchKernelGGL(rotate_kernel<true>, grid, dim3(64), 0, st, in, n, D, M, out, zero, nzero);
+  else
+    hipLaunchKernelGGL(rotate_kernel<false>, grid, dim3(64), 0, st, in, n, D, M, out, zero, nzero);
   return hipGetLastError();
 }
 

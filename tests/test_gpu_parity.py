@@ -74,6 +74,13 @@ def test_rotation_bit_exact(cfg1):
     idx2 = qg.qg_build_index(T(Xi), T(G2), T(M2), 0)
     out2 = idx2.rotate(T(Qi)).cpu().numpy()
     assert np.array_equal(out2, oracle.rotate(M2, Qi))
+    # rows that start 4 bytes past a 16-byte boundary take the one-column-per-lane loads
+    buf = torch.zeros(Qi.size + 1, dtype=torch.float32, device=DEV)
+    buf[1:] = T(Qi).reshape(-1)
+    Qv = buf[1:].view(Qi.shape)
+    assert Qv.data_ptr() % 16 == 4
+    out3 = idx2.rotate(Qv).cpu().numpy()
+    assert np.array_equal(out3, oracle.rotate(M2, Qi))
 
 
 def test_encode_bit_exact_cfg1(cfg1):
