@@ -1690,14 +1690,21 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
 
 // Minimum wavefronts per SIMD the register allocator must allow (1: no
 // constraint).  LDS-beam kernels with D <= 256: 6 for the stop-only and
-// mixed-batch modes.  Register-beam kernels with D = 128: 6 for the two-word
-// beam and for mixed batches, where the allocator would otherwise take a few
-// registers more than 80 and drop to 5 wavefronts per SIMD; the few values it
-// then keeps in scratch cost less than the lost wavefront (5-17% faster at
-// 10,000 and 80,000 queries).  The one-word plain kernel fits in 80 anyway.
+// mixed-batch modes.  Register-beam kernels with R = 32, plain or mixed
+// batches, D = 128 (but the one-word plain kernel, which fits in 80 registers
+// anyway) and D = 96: 6, where the allocator would otherwise take 82-96
+// registers and drop to 5 wavefronts per SIMD; the few values it then keeps in
+// scratch (16-56 bytes per lane) cost less than the lost wavefront (5-17%
+// faster at 10,000 and 80,000 queries).  Measured not to pay: 4 for D = 768
+// (32 bytes of scratch, 1-2% slower); R = 64 would spill over 100 bytes.
 template <int D, int R, int LS, int NB>
 constexpr int waves_hint() {
-  if constexpr (NB > 0) return D == 128 && ((NB == 2 && LS == kLsOff) || LS == kMixed) ? 6 : 1;
+  if constexpr (NB > 0) {
+    constexpr bool mode = LS == kLsOff || LS == kMixed;
+    if constexpr (R == 32 && D == 128) return mode && !(NB == 1 && LS == kLsOff) ? 6 : 1;
+    if constexpr (R == 32 && D == 96) return mode ? 6 : 1;
+    return 1;
+  }
   return D > 256 ? 1 : (mlp_in_lds<LS> || LS == kMixed) ? 6 : 1;
 }
 
