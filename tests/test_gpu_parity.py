@@ -102,6 +102,8 @@ def test_encode_bit_exact_shapes(D, R, cfg):
     idx = qg.qg_build_index(T(X), T(G), T(M), synth.medoid(X))
     got = idx.blocks().cpu().numpy()
     assert np.array_equal(got, oracle.encode(X, G, M))
+    # the queries' rotation at this width (2 x 2 tiles per wavefront when D > 256; 20 rows: a ragged block)
+    assert np.array_equal(idx.rotate(T(Q)).cpu().numpy(), oracle.rotate(M, Q))
 
 
 def test_estimate_bit_exact(cfg1):
