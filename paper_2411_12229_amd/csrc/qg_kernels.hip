@@ -1712,15 +1712,15 @@ __device__ void search_one_rb(const SearchArgs& a, int64_t q, uint8_t* lds, cons
 // anyway) and D = 96: 6, where the allocator would otherwise take 82-96
 // registers and drop to 5 wavefronts per SIMD; the few values it then keeps in
 // scratch (16-56 bytes per lane) cost less than the lost wavefront (5-17%
-// faster at 10,000 and 80,000 queries).  The stop-only register-beam kernel at
-// D = 128, R = 32: 6 as well (107 registers and 4 wavefronts otherwise; 48-64
-// bytes of scratch; 8-16% faster).  Measured not to pay: 4 for D = 768 (32
+// faster at 10,000 and 80,000 queries).  The stop kernels with the beam in
+// registers at D = 128, R = 32 (one query or a mixed batch): 6 as well (107-115
+// registers and 4 wavefronts otherwise; 48-84 bytes of scratch; 6-16% faster).  Measured not to pay: 4 for D = 768 (32
 // bytes of scratch, 1-2% slower); R = 64 would spill over 100 bytes.
 template <int D, int R, int LS, int NB>
 constexpr int waves_hint() {
   if constexpr (NB > 0) {
     constexpr bool mode = LS == kLsOff || LS == kMixed;
-    if constexpr (R == 32 && D == 128 && LS == kLsStop) return 6;
+    if constexpr (R == 32 && D == 128 && (LS == kLsStop || LS == kMixedStop)) return 6;
     if constexpr (R == 32 && D == 128) return mode && !(NB == 1 && LS == kLsOff) ? 6 : 1;
     if constexpr (R == 32 && D == 96) return mode ? 6 : 1;
     return 1;
