@@ -187,7 +187,9 @@ int qg_search_mixed_stop(const qg_index *idx, const float *queries, int64_t nq, 
 
 /* out[n][d] = M in[n][d] for the index's rotation M (Eq. rotation), on the
  * matrix cores: fp64 products accumulated over j ascending, rounded once to
- * fp32.  This is the first step of qg_search, exposed for checking. */
+ * fp32.  This is the first step of qg_search, exposed for checking.  Any
+ * 4-byte-aligned `in` works; rows that start 16-byte aligned take wider loads
+ * (the result is the same either way). */
 int qg_rotate(const qg_index *idx, const float *in, int64_t n, float *out);
 
 /* The estimator alone (Sec. 3.1.1, Eq. 3.1): for query i and vertex
